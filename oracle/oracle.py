@@ -1,0 +1,131 @@
+"""Python face of the FP64 CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares nothing with the GPU package:
+it loads ``oracle/libsnx_oracle.so`` (plain C, gcc) through ctypes and works on
+numpy arrays.
+
+Stage functions (the C file cites the paper's passage for each):
+  denoise(D, nf)            masked LSQ plane-fit intercept (filter)
+  affine(Dt, ng)            a1, a2 and definedness (anchored masked LSQ)
+  normals(Dt, a1, a2, ...)  normal from the constraint-vector cross product
+  components(D, k, t)       min-index labels of covered-depth components
+  point_cloud(Dt, n, cam)   back-projected points with normals
+  pipeline(D, cam, ...)     all of the above, in order
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsnx_oracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_u8 = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+_i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build  # compile the checker on first use
+        _build.build()
+    lib = C.CDLL(_LIB_PATH)
+    lib.snxo_denoise.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, _dp]
+    lib.snxo_affine.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _u8]
+    lib.snxo_normals.argtypes = [_dp, _dp, _dp, _u8, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
+    lib.snxo_components.argtypes = [_fp, C.c_int, C.c_int, C.c_float, C.c_float, _i32,
+                                    C.POINTER(C.c_int64)]
+    lib.snxo_point_cloud.argtypes = [_dp, _dp, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
+    lib.snxo_num_threads.argtypes = []
+    for f in ("snxo_denoise", "snxo_affine", "snxo_normals", "snxo_components",
+              "snxo_point_cloud", "snxo_num_threads"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def num_threads() -> int:
+    return int(load().snxo_num_threads())
+
+
+def default_min_support(ng: int) -> int:
+    """Default minimum support of the gradient window: half the window, rounded up."""
+    return int(math.ceil(ng * ng / 2.0))
+
+
+def _as_f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def denoise(D, nf: int, min_support: int = 0) -> np.ndarray:
+    D = _as_f64(D)
+    H, W = D.shape
+    out = np.empty_like(D)
+    if load().snxo_denoise(D, W, H, int(nf), int(min_support), out) != 0:
+        raise ValueError("oracle denoise: bad arguments")
+    return out
+
+
+def affine(Dt, ng: int, min_support: int | None = None):
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    ms = default_min_support(ng) if min_support is None else int(min_support)
+    a1 = np.empty_like(Dt)
+    a2 = np.empty_like(Dt)
+    d = np.empty((H, W), np.uint8)
+    if load().snxo_affine(Dt, W, H, int(ng), ms, a1, a2, d) != 0:
+        raise ValueError("oracle affine: bad arguments")
+    return a1, a2, d.astype(bool)
+
+
+def normals(Dt, a1, a2, defined, cam) -> np.ndarray:
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    out = np.empty((H, W, 3), np.float64)
+    load().snxo_normals(Dt, _as_f64(a1), _as_f64(a2),
+                        np.ascontiguousarray(defined, dtype=np.uint8), W, H,
+                        cam.fx, cam.fy, cam.baseline, cam.u0, cam.v0, out)
+    return out
+
+
+def components(D, k_rel: float = 0.1, t_abs: float = 1.0):
+    D = np.ascontiguousarray(D, dtype=np.float32)
+    H, W = D.shape
+    lab = np.empty((H, W), np.int32)
+    n = C.c_int64(0)
+    if load().snxo_components(D, W, H, C.c_float(k_rel), C.c_float(t_abs), lab,
+                              C.byref(n)) != 0:
+        raise MemoryError("oracle components")
+    return lab, int(n.value)
+
+
+def point_cloud(Dt, nrm, cam) -> np.ndarray:
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    out = np.empty((H, W, 6), np.float64)
+    load().snxo_point_cloud(Dt, _as_f64(nrm), W, H, cam.fx, cam.fy,
+                            cam.baseline, cam.u0, cam.v0, out)
+    return out
+
+
+def pipeline(D, cam, nf: int = 3, ng: int = 9, min_support_f: int = 0,
+             min_support_g: int | None = None, k_rel: float = 0.1,
+             t_abs: float = 1.0) -> dict:
+    """Every stage in the paper's order on one float32 disparity map."""
+    D32 = np.ascontiguousarray(D, dtype=np.float32)
+    Dt = denoise(D32.astype(np.float64), nf, min_support_f)
+    a1, a2, dfn = affine(Dt, ng, min_support_g)
+    nrm = normals(Dt, a1, a2, dfn, cam)
+    lab, ncomp = components(D32, k_rel, t_abs)
+    pts = point_cloud(Dt, nrm, cam)
+    return {"denoised": Dt, "a1": a1, "a2": a2, "defined": dfn, "normals": nrm,
+            "labels": lab, "num_components": ncomp, "points": pts}
