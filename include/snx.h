@@ -1,0 +1,227 @@
+/*
+ * snx.h -- C ABI of the MI355X (gfx950) surface-normal-from-disparity library.
+ *
+ * The library implements the per-pixel path of "Robust and Real-time Surface
+ * Normal Estimation from Stereo Disparities using Affine Transformations"
+ * (Kariko, Faisal, Hajder): a rectified disparity map goes through a denoising
+ * filter, per-pixel disparity gradients, the rectified affine transform A, the
+ * surface normal from A and the camera, connected surface components, and comes
+ * out as a dense oriented point cloud (abstract; Sec. 2-3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Image buffers are DEVICE pointers (hipMalloc'd or a torch tensor's
+ *    data_ptr()), row-major, with row strides given in ELEMENTS (>= width).
+ *    The caller owns every buffer; the library never retains or frees one.
+ *  - u is the column, v the row (downwards); pixel centres are at integers.
+ *  - Disparity is the positive D = u_left - u_right = f_x * b / z.  (The paper's
+ *    d is u_right - u_left = -D; every formula below is stated for D.)
+ *  - A disparity is valid iff it is finite and > 0.  Invalid pixels are data,
+ *    not errors: they produce NaN in float outputs and -1 in labels.  Pixels
+ *    outside the image are invalid (no padding, clamping or mirroring).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work; it returns once arguments are validated and kernels are
+ *    launched.  Arguments are validated before anything is launched: an invalid
+ *    call returns SNX_ERR_ARG / SNX_ERR_UNSUPPORTED / SNX_ERR_WORKSPACE and
+ *    writes nothing.  A failed launch returns SNX_ERR_HIP.
+ *  - width == 0 or height == 0 is a valid empty call (buffers may be NULL).
+ *  - width * height must be < 2^31 (labels are int32 linear indices).
+ *  - Results are bit-identical from run to run; the fused and the separate
+ *    calls produce bit-identical outputs for the same inputs.
+ *  - snx_last_error() returns a message for the calling thread's last failure.
+ */
+#ifndef SNX_H
+#define SNX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum snx_status {
+    SNX_OK = 0,
+    SNX_ERR_ARG = 1,          /* NULL pointer, bad size, stride, window or camera */
+    SNX_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. window too large)   */
+    SNX_ERR_WORKSPACE = 3,    /* workspace missing or too small                   */
+    SNX_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed       */
+    SNX_ERR_MODEL = 5         /* reserved for learned-filter models               */
+} snx_status;
+
+/* Rectified pin-hole pair (Sec. 2, projections Pi_1 and Pi_2): focal lengths in
+ * pixels, baseline in the unit the point cloud is wanted in, principal point in
+ * pixels.  fx, fy, baseline must be finite and > 0; u0, v0 finite. */
+typedef struct snx_camera {
+    float fx, fy, baseline, u0, v0;
+} snx_camera;
+
+/* Denoising filter.  window = n_f (odd, 1..63): the output at a valid pixel c is
+ * the intercept h of the least-squares plane D_i ~ h + g_u v_ix + g_v v_iy
+ * fitted to the valid pixels i of the n_f x n_f window around c (the
+ * over-determined LSQ of Sec. 3.2 with a constant column).  On a full window
+ * this is the box mean; n_f = 1 is the identity (the paper's unfiltered mode).
+ * The centre value passes through unchanged when fewer than
+ * max(3, min_support) pixels are valid or the 3x3 normal matrix is singular.
+ * mode must be SNX_FILTER_LSQ; model must be NULL. */
+#define SNX_FILTER_LSQ 0
+typedef struct snx_denoise_params {
+    int32_t window;
+    int32_t min_support;
+    int32_t mode;
+    int32_t reserved;
+    const void *model;
+} snx_denoise_params;
+
+/* Gradient window.  window = n_g (odd, 3..63).  The slope at a valid pixel c is
+ * the anchored LSQ of Sec. 3.2-3.3 over the valid pixels i != c of the n_g x n_g
+ * window, with alpha, beta, gamma summed over that (possibly masked) support
+ * (the two-pass scheme of Sec. 3.4).  It is defined iff at least min_support
+ * such pixels exist and alpha*gamma - beta^2 > 0; min_support <= 0 selects the
+ * default ceil(n_g^2 / 2). */
+typedef struct snx_normal_params {
+    int32_t window;
+    int32_t min_support;
+} snx_normal_params;
+
+/* Component edge predicate: 4-neighbours p, q are joined iff both are valid and
+ *   |D_p - D_q| <= max(t_abs, k_rel * min(D_p, D_q))
+ * evaluated in binary64 on the float32 inputs (the pairwise form of the
+ * covered-depth stopping rule of Sec. 3.4).  k_rel, t_abs finite and >= 0. */
+typedef struct snx_component_params {
+    float k_rel;   /* default 0.1 */
+    float t_abs;   /* default 1.0 px */
+} snx_component_params;
+
+/* One point of the dense oriented point cloud, 32 bytes. */
+#define SNX_POINT_DEFINED  1u   /* position and normal are defined            */
+#define SNX_POINT_LABELLED 2u   /* label >= 0 (the raw disparity was valid)    */
+typedef struct snx_point {
+    float x, y, z;      /* camera frame, x right, y down, z forward       */
+    float nx, ny, nz;   /* unit normal facing the camera                  */
+    int32_t label;      /* component label (minimum linear index) or -1    */
+    uint32_t flags;     /* SNX_POINT_* bits                                */
+} snx_point;
+
+/* ---------------------------------------------------------------------------
+ * snx_denoise -- the filter (see snx_denoise_params).
+ *   disp [height x disp_stride] float32 in; out [height x out_stride] float32
+ *   out (NaN where the input is invalid).  disp and out must not overlap.
+ * ------------------------------------------------------------------------- */
+snx_status snx_denoise(const float *disp, int64_t disp_stride,
+                       float *out, int64_t out_stride,
+                       int32_t width, int32_t height,
+                       const snx_denoise_params *params, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_affine_normals -- gradients, A and normals from a (denoised) disparity.
+ * Gradient (g_u, g_v) as in snx_normal_params; then (Sec. 2 eq. affine_mtx and
+ * Sec. 3.2) A = [[a1, a2], [0, 1]] with a1 = 1 - g_u, a2 = -g_v; then the normal
+ * of Sec. 3.1, computed as n = -m / |m| with
+ *   m = (f_x g_u, f_y g_v, D_c - (u - u0) g_u - (v - v0) g_v),
+ * which is the cross product of the paper's two constraint vectors divided by
+ * b z (the printed closed form has the sign of its b term flipped; m . X =
+ * f_x b > 0, so n always faces the camera).
+ *   disp_dn [height x stride] float32 in.
+ *   affine  NULL or 2 planes (a1 then a2), each [height x out_stride], the second
+ *           starting at affine + height * out_stride.
+ *   normals NULL or 3 planes (nx, ny, nz) laid out the same way.
+ *   Undefined pixels get NaN in every plane.
+ * ------------------------------------------------------------------------- */
+snx_status snx_affine_normals(const float *disp_dn, int64_t stride,
+                              int32_t width, int32_t height,
+                              const snx_camera *cam,
+                              const snx_normal_params *params,
+                              float *affine, float *normals, int64_t out_stride,
+                              void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_components -- connected surface components of the RAW disparity under the
+ * predicate of snx_component_params.  labels[v * label_stride + u] receives the
+ * smallest linear index v' * width + u' of the pixel's component, or -1 if the
+ * pixel is invalid.  num_components: NULL or a device int32 that receives the
+ * number of components.  workspace: device memory of at least
+ * snx_components_workspace_size(width, height) bytes, owned by the caller; its
+ * contents need no initialisation and are scratch after the call.  Concurrent
+ * calls need distinct workspaces.
+ * ------------------------------------------------------------------------- */
+size_t snx_components_workspace_size(int32_t width, int32_t height);
+snx_status snx_components(const float *disp_raw, int64_t stride,
+                          int32_t width, int32_t height,
+                          const snx_component_params *params,
+                          int32_t *labels, int64_t label_stride,
+                          int32_t *num_components,
+                          void *workspace, size_t workspace_bytes,
+                          void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_point_cloud -- dense oriented point cloud (abstract; Sec. 2 projections).
+ * Where the normal is defined: z = f_x b / D, x = (u - u0) z / f_x,
+ * y = (v - v0) z / f_y with D the denoised disparity, plus the normal; elsewhere
+ * NaN coordinates and normal.  label is copied from `labels` (NULL: -1).
+ *   disp_dn [height x disp_stride], normals 3 planes [height x normals_stride]
+ *   (as written by snx_affine_normals), labels [height x label_stride] or NULL,
+ *   out: width * height records, row-major, contiguous.
+ * ------------------------------------------------------------------------- */
+snx_status snx_point_cloud(const float *disp_dn, int64_t disp_stride,
+                           const float *normals, int64_t normals_stride,
+                           const int32_t *labels, int64_t label_stride,
+                           int32_t width, int32_t height,
+                           const snx_camera *cam, snx_point *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_oriented_point_cloud -- filter, gradients, A, normal and point records in
+ * ONE kernel, given component labels already computed by snx_components on the
+ * same raw disparity.  Outputs are bit-identical to snx_denoise ->
+ * snx_affine_normals -> snx_point_cloud with the same parameters.
+ *   disp [height x stride] raw float32; labels [height x label_stride] int32
+ *   (input; NULL gives label -1 in every record); disp_dn, affine, normals: NULL
+ *   or as in the separate calls (out_stride); points: width * height records.
+ * ------------------------------------------------------------------------- */
+snx_status snx_oriented_point_cloud(const float *disp, int64_t stride,
+                                    int32_t width, int32_t height,
+                                    const snx_camera *cam,
+                                    const snx_denoise_params *denoise,
+                                    const snx_normal_params *normal,
+                                    const int32_t *labels, int64_t label_stride,
+                                    float *disp_dn, float *affine, float *normals,
+                                    int64_t out_stride, snx_point *points,
+                                    void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_pipeline -- the whole path in the fewest passes: snx_components on the
+ * raw disparity, then snx_oriented_point_cloud (one fused kernel for filter,
+ * gradients, A, normal and point records).  Outputs are bit-identical to snx_denoise -> snx_affine_normals ->
+ * snx_components -> snx_point_cloud with the same parameters.
+ *   disp_dn, affine, normals: NULL or as in the separate calls (out_stride).
+ *   labels [height x label_stride] required; num_components NULL or device int32.
+ *   points: width * height records (required).
+ *   workspace: at least snx_pipeline_workspace_size(width, height) bytes.
+ * ------------------------------------------------------------------------- */
+size_t snx_pipeline_workspace_size(int32_t width, int32_t height);
+snx_status snx_pipeline(const float *disp, int64_t stride,
+                        int32_t width, int32_t height,
+                        const snx_camera *cam,
+                        const snx_denoise_params *denoise,
+                        const snx_normal_params *normal,
+                        const snx_component_params *comp,
+                        float *disp_dn, float *affine, float *normals,
+                        int64_t out_stride,
+                        int32_t *labels, int64_t label_stride,
+                        int32_t *num_components,
+                        snx_point *points,
+                        void *workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* Status name ("SNX_OK", ...); never NULL. */
+const char *snx_status_string(snx_status status);
+/* Message describing the calling thread's last failed call ("" if none). */
+const char *snx_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t snx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNX_H */

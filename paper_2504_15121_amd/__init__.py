@@ -1,0 +1,19 @@
+"""MI355X-native surface normals and oriented point clouds from rectified disparities.
+
+The computation lives in hand-written HIP kernels for gfx950 behind the C ABI of
+``include/snx.h`` (``libsnx.so``); this package only marshals torch device
+tensors into those calls.  Entry points (same names as the C functions):
+
+    snx_denoise, snx_affine_normals, snx_components, snx_point_cloud,
+    snx_oriented_point_cloud, snx_pipeline, snx_components_workspace_size,
+    snx_pipeline_workspace_size
+"""
+from ._lib import (POINT_DEFINED, POINT_LABELLED, SnxError, load, snx_affine_normals,
+                   snx_components, snx_components_workspace_size, snx_denoise,
+                   snx_oriented_point_cloud, snx_pipeline, snx_pipeline_workspace_size,
+                   snx_point_cloud)
+
+__all__ = ["load", "SnxError", "POINT_DEFINED", "POINT_LABELLED", "snx_denoise",
+           "snx_affine_normals", "snx_components", "snx_components_workspace_size",
+           "snx_point_cloud", "snx_oriented_point_cloud", "snx_pipeline",
+           "snx_pipeline_workspace_size"]

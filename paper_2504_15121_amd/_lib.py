@@ -1,0 +1,243 @@
+"""ctypes binding of libsnx.so: argument marshalling only.
+
+Every function here has the name of the C entry point it calls and forwards
+torch device tensors as raw pointers plus strides; all computation happens in the
+HIP kernels.  The library must have been built (``__graft_entry__.build()``);
+there is no fallback of any kind: a missing library raises at load time.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnx.so")
+
+SNX_OK = 0
+STATUS = {0: "SNX_OK", 1: "SNX_ERR_ARG", 2: "SNX_ERR_UNSUPPORTED", 3: "SNX_ERR_WORKSPACE",
+          4: "SNX_ERR_HIP", 5: "SNX_ERR_MODEL"}
+
+POINT_DEFINED = 1
+POINT_LABELLED = 2
+
+
+class SnxError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class snx_camera(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("baseline", C.c_float),
+                ("u0", C.c_float), ("v0", C.c_float)]
+
+
+class snx_denoise_params(C.Structure):
+    _fields_ = [("window", C.c_int32), ("min_support", C.c_int32), ("mode", C.c_int32),
+                ("reserved", C.c_int32), ("model", C.c_void_p)]
+
+
+class snx_normal_params(C.Structure):
+    _fields_ = [("window", C.c_int32), ("min_support", C.c_int32)]
+
+
+class snx_component_params(C.Structure):
+    _fields_ = [("k_rel", C.c_float), ("t_abs", C.c_float)]
+
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_SZ = C.c_size_t
+
+SIGNATURES = {
+    "snx_denoise": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_denoise_params), _P]),
+    "snx_affine_normals": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                                  C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
+    "snx_components_workspace_size": (_SZ, [_I32, _I32]),
+    "snx_components": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_component_params), _P, _I64,
+                              _P, _P, _SZ, _P]),
+    "snx_point_cloud": (_I32, [_P, _I64, _P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                               _P, _P]),
+    "snx_oriented_point_cloud": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                                        C.POINTER(snx_denoise_params),
+                                        C.POINTER(snx_normal_params), _P, _I64, _P, _P, _P,
+                                        _I64, _P, _P]),
+    "snx_pipeline_workspace_size": (_SZ, [_I32, _I32]),
+    "snx_pipeline": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                            C.POINTER(snx_denoise_params), C.POINTER(snx_normal_params),
+                            C.POINTER(snx_component_params), _P, _P, _P, _I64, _P, _I64, _P, _P,
+                            _P, _SZ, _P]),
+    "snx_status_string": (C.c_char_p, [_I32]),
+    "snx_last_error": (C.c_char_p, []),
+    "snx_version": (_I32, []),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsnx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first "
+                          "(there is no non-HIP fallback)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != SNX_OK:
+        raise SnxError(status, load().snx_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _img(t, dtype, name):
+    import torch
+    if t.dtype != dtype or t.dim() != 2 or not t.is_cuda or t.stride(1) != 1:
+        raise ValueError(f"{name}: need a CUDA {dtype} (H, W) tensor with unit column stride")
+    return t.stride(0)
+
+
+def _planes(t, n, H, W, name):
+    import torch
+    if t is None:
+        return None
+    if (t.dtype != torch.float32 or t.dim() != 3 or t.shape[0] != n or t.shape[1] != H
+            or t.shape[2] < W or not t.is_cuda or t.stride(2) != 1
+            or t.stride(0) != t.shape[1] * t.stride(1)):
+        raise ValueError(f"{name}: need a CUDA float32 ({n}, H, S) plane tensor, S >= W")
+    return t.stride(1)
+
+
+def camera(cam) -> snx_camera:
+    """snx_camera from anything with fx, fy, baseline, u0, v0 attributes."""
+    return snx_camera(cam.fx, cam.fy, cam.baseline, cam.u0, cam.v0)
+
+
+def snx_denoise(disp, out, window=3, min_support=0, stream=None):
+    H, W = disp.shape
+    p = snx_denoise_params(window, min_support, 0, 0, None)
+    _check(load().snx_denoise(_ptr(disp), _img(disp, disp.dtype, "disp"), _ptr(out),
+                              _img(out, disp.dtype, "out"), W, H, C.byref(p), _stream(stream)))
+
+
+def snx_affine_normals(disp_dn, cam, affine=None, normals=None, window=9, min_support=0,
+                       stream=None):
+    import torch
+    H, W = disp_dn.shape
+    ld = _img(disp_dn, torch.float32, "disp_dn")
+    la = _planes(affine, 2, H, W, "affine")
+    ln = _planes(normals, 3, H, W, "normals")
+    if la is not None and ln is not None and la != ln:
+        raise ValueError("affine and normals must share one row stride")
+    out_ld = la if la is not None else (ln if ln is not None else W)
+    p = snx_normal_params(window, min_support)
+    c = camera(cam)
+    _check(load().snx_affine_normals(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
+                                     _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
+
+
+def snx_components_workspace_size(width, height):
+    return int(load().snx_components_workspace_size(width, height))
+
+
+def snx_components(disp, labels, workspace, num_components=None, k_rel=0.1, t_abs=1.0,
+                   stream=None):
+    import torch
+    H, W = disp.shape
+    p = snx_component_params(k_rel, t_abs)
+    _check(load().snx_components(_ptr(disp), _img(disp, torch.float32, "disp"), W, H,
+                                 C.byref(p), _ptr(labels), _img(labels, torch.int32, "labels"),
+                                 _ptr(num_components), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def _points(t, H, W):
+    if t.numel() * t.element_size() < H * W * 32 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError("points: need a contiguous CUDA buffer of width*height*32 bytes")
+
+
+def snx_point_cloud(disp_dn, normals, labels, cam, out, stream=None):
+    import torch
+    H, W = disp_dn.shape
+    ld = _img(disp_dn, torch.float32, "disp_dn")
+    ln = _planes(normals, 3, H, W, "normals")
+    ll = _img(labels, torch.int32, "labels") if labels is not None else 0
+    _points(out, H, W)
+    c = camera(cam)
+    _check(load().snx_point_cloud(_ptr(disp_dn), ld, _ptr(normals), ln, _ptr(labels), ll, W, H,
+                                  C.byref(c), _ptr(out), _stream(stream)))
+
+
+def _out_stride(disp_dn, affine, normals, H, W):
+    import torch
+    lds = []
+    if disp_dn is not None:
+        lds.append(_img(disp_dn, torch.float32, "disp_dn"))
+    for t, n, name in ((affine, 2, "affine"), (normals, 3, "normals")):
+        if t is not None:
+            lds.append(_planes(t, n, H, W, name))
+    if len(set(lds)) > 1:
+        raise ValueError("disp_dn, affine and normals must share one row stride")
+    return lds[0] if lds else W
+
+
+def snx_oriented_point_cloud(disp, cam, points, labels=None, disp_dn=None, affine=None,
+                             normals=None, filter_window=3, filter_min_support=0,
+                             normal_window=9, normal_min_support=0, stream=None):
+    import torch
+    H, W = disp.shape
+    ld = _img(disp, torch.float32, "disp")
+    out_ld = _out_stride(disp_dn, affine, normals, H, W)
+    ll = _img(labels, torch.int32, "labels") if labels is not None else 0
+    _points(points, H, W)
+    dp = snx_denoise_params(filter_window, filter_min_support, 0, 0, None)
+    np_ = snx_normal_params(normal_window, normal_min_support)
+    c = camera(cam)
+    _check(load().snx_oriented_point_cloud(_ptr(disp), ld, W, H, C.byref(c), C.byref(dp),
+                                           C.byref(np_), _ptr(labels), ll, _ptr(disp_dn),
+                                           _ptr(affine), _ptr(normals), out_ld, _ptr(points),
+                                           _stream(stream)))
+
+
+def snx_pipeline_workspace_size(width, height):
+    return int(load().snx_pipeline_workspace_size(width, height))
+
+
+def snx_pipeline(disp, cam, labels, points, workspace, num_components=None, disp_dn=None,
+                 affine=None, normals=None, filter_window=3, filter_min_support=0,
+                 normal_window=9, normal_min_support=0, k_rel=0.1, t_abs=1.0, stream=None):
+    import torch
+    H, W = disp.shape
+    ld = _img(disp, torch.float32, "disp")
+    out_ld = _out_stride(disp_dn, affine, normals, H, W)
+    _points(points, H, W)
+    dp = snx_denoise_params(filter_window, filter_min_support, 0, 0, None)
+    np_ = snx_normal_params(normal_window, normal_min_support)
+    cp = snx_component_params(k_rel, t_abs)
+    c = camera(cam)
+    _check(load().snx_pipeline(_ptr(disp), ld, W, H, C.byref(c), C.byref(dp), C.byref(np_),
+                               C.byref(cp), _ptr(disp_dn), _ptr(affine), _ptr(normals), out_ld,
+                               _ptr(labels), _img(labels, torch.int32, "labels"),
+                               _ptr(num_components), _ptr(points), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)))

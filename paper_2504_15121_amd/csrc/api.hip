@@ -1,0 +1,345 @@
+// C ABI of libsnx: argument validation, workspace carving and kernel launches.
+// Every entry point validates all arguments before the first HIP call, so an
+// invalid call enqueues nothing and writes nothing.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "snx_internal.hpp"
+
+namespace {
+
+thread_local char g_err[256] = "";
+
+snx_status fail(snx_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+snx_status fail(snx_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+snx_status hip_fail(hipError_t e, const char *where)
+{
+    (void)hipGetLastError();  // clear the sticky launch error
+    return fail(SNX_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool size_ok(int32_t w, int32_t h) { return w >= 0 && h >= 0 && (int64_t)w * h < (1LL << 31); }
+
+bool cam_ok(const snx_camera *c)
+{
+    return c && isfinite(c->fx) && c->fx > 0 && isfinite(c->fy) && c->fy > 0 &&
+           isfinite(c->baseline) && c->baseline > 0 && isfinite(c->u0) && isfinite(c->v0);
+}
+
+snx_status check_image(const void *p, int64_t stride, int32_t w, const char *name)
+{
+    if (!p) return fail(SNX_ERR_ARG, "%s is NULL", name);
+    if (stride < w) return fail(SNX_ERR_ARG, "%s stride %lld < width %d", name, (long long)stride, w);
+    return SNX_OK;
+}
+
+snx_status check_denoise(const snx_denoise_params *p)
+{
+    if (!p) return fail(SNX_ERR_ARG, "denoise params are NULL");
+    if (p->window < 1 || p->window % 2 == 0)
+        return fail(SNX_ERR_ARG, "filter window %d must be odd and >= 1", p->window);
+    if (p->window > snx::kMaxWindow)
+        return fail(SNX_ERR_UNSUPPORTED, "filter window %d > %d", p->window, snx::kMaxWindow);
+    if (p->mode != SNX_FILTER_LSQ) return fail(SNX_ERR_UNSUPPORTED, "filter mode %d", p->mode);
+    if (p->model) return fail(SNX_ERR_ARG, "LSQ filter takes no model");
+    return SNX_OK;
+}
+
+snx_status check_normal(const snx_normal_params *p)
+{
+    if (!p) return fail(SNX_ERR_ARG, "normal params are NULL");
+    if (p->window < 3 || p->window % 2 == 0)
+        return fail(SNX_ERR_ARG, "gradient window %d must be odd and >= 3", p->window);
+    if (p->window > snx::kMaxWindow)
+        return fail(SNX_ERR_UNSUPPORTED, "gradient window %d > %d", p->window, snx::kMaxWindow);
+    return SNX_OK;
+}
+
+snx_status check_comp(const snx_component_params *p)
+{
+    if (!p) return fail(SNX_ERR_ARG, "component params are NULL");
+    if (!(isfinite(p->k_rel) && p->k_rel >= 0) || !(isfinite(p->t_abs) && p->t_abs >= 0))
+        return fail(SNX_ERR_ARG, "component thresholds must be finite and >= 0");
+    return SNX_OK;
+}
+
+int need_g(const snx_normal_params *p)
+{
+    return p->min_support > 0 ? p->min_support : (p->window * p->window + 1) / 2;
+}
+
+int need_f(const snx_denoise_params *p) { return p->min_support > 3 ? p->min_support : 3; }
+
+size_t ws_components(int32_t w, int32_t h)
+{
+    if (!size_ok(w, h)) return 0;
+    return 256 + (size_t)w * (size_t)h * sizeof(int32_t);
+}
+
+snx_status fill_stencil(snx::StencilArgs &a, const float *src, int64_t ld, int32_t w, int32_t h,
+                        int rf, int rg, int nf, int ng, const snx_camera *cam)
+{
+    memset(&a, 0, sizeof a);
+    a.src = src;
+    a.ld_src = ld;
+    a.W = w;
+    a.H = h;
+    a.rf = rf;
+    a.rg = rg;
+    a.need_f = nf;
+    a.need_g = ng;
+    if (cam) {
+        a.fx = cam->fx; a.fy = cam->fy; a.b = cam->baseline; a.u0 = cam->u0; a.v0 = cam->v0;
+    }
+    a.th = snx::stencil_pick_tile_height(rf, rg);
+    if (a.th == 0) return fail(SNX_ERR_UNSUPPORTED, "windows too large for one tile in LDS");
+    return SNX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *snx_status_string(snx_status s)
+{
+    switch (s) {
+    case SNX_OK: return "SNX_OK";
+    case SNX_ERR_ARG: return "SNX_ERR_ARG";
+    case SNX_ERR_UNSUPPORTED: return "SNX_ERR_UNSUPPORTED";
+    case SNX_ERR_WORKSPACE: return "SNX_ERR_WORKSPACE";
+    case SNX_ERR_HIP: return "SNX_ERR_HIP";
+    case SNX_ERR_MODEL: return "SNX_ERR_MODEL";
+    }
+    return "SNX_ERR_UNKNOWN";
+}
+
+const char *snx_last_error(void) { return g_err; }
+
+int32_t snx_version(void) { return 100; }
+
+snx_status snx_denoise(const float *disp, int64_t disp_stride, float *out, int64_t out_stride,
+                       int32_t width, int32_t height, const snx_denoise_params *params,
+                       void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_denoise(params);
+    if (st) return st;
+    if (width == 0 || height == 0) return SNX_OK;
+    if ((st = check_image(disp, disp_stride, width, "disp"))) return st;
+    if ((st = check_image(out, out_stride, width, "out"))) return st;
+    snx::StencilArgs a;
+    if ((st = fill_stencil(a, disp, disp_stride, width, height, params->window / 2, 0,
+                           need_f(params), 0, nullptr)))
+        return st;
+    a.dn = out;
+    a.ld_dn = out_stride;
+    hipError_t e = snx::launch_stencil(a, (hipStream_t)stream);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_denoise");
+}
+
+snx_status snx_affine_normals(const float *disp_dn, int64_t stride, int32_t width, int32_t height,
+                              const snx_camera *cam, const snx_normal_params *params,
+                              float *affine, float *normals, int64_t out_stride, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_normal(params);
+    if (st) return st;
+    if (!cam_ok(cam)) return fail(SNX_ERR_ARG, "camera is NULL or not finite/positive");
+    if (width == 0 || height == 0) return SNX_OK;
+    if ((st = check_image(disp_dn, stride, width, "disp_dn"))) return st;
+    if (!affine && !normals) return fail(SNX_ERR_ARG, "affine and normals are both NULL");
+    if (out_stride < width) return fail(SNX_ERR_ARG, "out_stride < width");
+    snx::StencilArgs a;
+    if ((st = fill_stencil(a, disp_dn, stride, width, height, 0, params->window / 2, 0,
+                           need_g(params), cam)))
+        return st;
+    a.aff = affine;
+    a.nrm = normals;
+    a.ld_out = out_stride;
+    a.plane_out = out_stride * (int64_t)height;
+    hipError_t e = snx::launch_stencil(a, (hipStream_t)stream);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals");
+}
+
+size_t snx_components_workspace_size(int32_t width, int32_t height) { return ws_components(width, height); }
+
+static snx_status components_impl(const float *disp, int64_t stride, int32_t width, int32_t height,
+                                  const snx_component_params *p, int32_t *labels,
+                                  int64_t label_stride, int32_t *num_components, void *workspace,
+                                  size_t workspace_bytes, hipStream_t s, const char *who)
+{
+    snx::CclArgs c;
+    c.D = disp;
+    c.ld = stride;
+    c.W = width;
+    c.H = height;
+    c.k_rel = (double)p->k_rel;
+    c.t_abs = (double)p->t_abs;
+    c.labels = labels;
+    c.ld_lab = label_stride;
+    c.parent = label_stride == width ? labels : reinterpret_cast<int32_t *>(
+                                                    static_cast<char *>(workspace) + 256);
+    c.count = num_components;
+    (void)workspace_bytes;
+    hipError_t e = snx::launch_components(c, s);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, who);
+}
+
+snx_status snx_components(const float *disp_raw, int64_t stride, int32_t width, int32_t height,
+                          const snx_component_params *params, int32_t *labels,
+                          int64_t label_stride, int32_t *num_components, void *workspace,
+                          size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_comp(params);
+    if (st) return st;
+    if (width == 0 || height == 0) {
+        if (!num_components) return SNX_OK;
+        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, (hipStream_t)stream);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_components");
+    }
+    if ((st = check_image(disp_raw, stride, width, "disp_raw"))) return st;
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    if (!workspace || workspace_bytes < ws_components(width, height))
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_components(width, height));
+    return components_impl(disp_raw, stride, width, height, params, labels, label_stride,
+                           num_components, workspace, workspace_bytes, (hipStream_t)stream,
+                           "snx_components");
+}
+
+snx_status snx_point_cloud(const float *disp_dn, int64_t disp_stride, const float *normals,
+                           int64_t normals_stride, const int32_t *labels, int64_t label_stride,
+                           int32_t width, int32_t height, const snx_camera *cam, snx_point *out,
+                           void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (!cam_ok(cam)) return fail(SNX_ERR_ARG, "camera is NULL or not finite/positive");
+    if (width == 0 || height == 0) return SNX_OK;
+    snx_status st;
+    if ((st = check_image(disp_dn, disp_stride, width, "disp_dn"))) return st;
+    if ((st = check_image(normals, normals_stride, width, "normals"))) return st;
+    if (labels && label_stride < width) return fail(SNX_ERR_ARG, "label_stride < width");
+    if (!out) return fail(SNX_ERR_ARG, "out is NULL");
+    snx::CloudArgs a;
+    a.dn = disp_dn;
+    a.ld_dn = disp_stride;
+    a.nrm = normals;
+    a.ld_nrm = normals_stride;
+    a.plane_nrm = normals_stride * (int64_t)height;
+    a.labels = labels;
+    a.ld_lab = label_stride;
+    a.W = width;
+    a.H = height;
+    a.fx = cam->fx; a.fy = cam->fy; a.b = cam->baseline; a.u0 = cam->u0; a.v0 = cam->v0;
+    a.out = out;
+    hipError_t e = snx::launch_point_cloud(a, (hipStream_t)stream);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_point_cloud");
+}
+
+static snx_status fused_impl(const float *disp, int64_t stride, int32_t width, int32_t height,
+                             const snx_camera *cam, const snx_denoise_params *denoise,
+                             const snx_normal_params *normal, const int32_t *labels,
+                             int64_t label_stride, float *disp_dn, float *affine, float *normals,
+                             int64_t out_stride, snx_point *points, hipStream_t s, const char *who)
+{
+    snx::StencilArgs a;
+    snx_status st = fill_stencil(a, disp, stride, width, height, denoise->window / 2,
+                                 normal->window / 2, need_f(denoise), need_g(normal), cam);
+    if (st) return st;
+    a.dn = disp_dn;
+    a.ld_dn = out_stride;
+    a.aff = affine;
+    a.nrm = normals;
+    a.ld_out = out_stride;
+    a.plane_out = out_stride * (int64_t)height;
+    a.labels = labels;
+    a.ld_lab = label_stride;
+    a.rec = points;
+    hipError_t e = snx::launch_stencil(a, s);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, who);
+}
+
+static snx_status check_fused(const float *disp, int64_t stride, int32_t width, int32_t height,
+                              const snx_camera *cam, const snx_denoise_params *denoise,
+                              const snx_normal_params *normal, float *disp_dn, float *affine,
+                              float *normals, int64_t out_stride, snx_point *points)
+{
+    snx_status st;
+    if ((st = check_denoise(denoise)) || (st = check_normal(normal))) return st;
+    if (!cam_ok(cam)) return fail(SNX_ERR_ARG, "camera is NULL or not finite/positive");
+    if (width == 0 || height == 0) return SNX_OK;
+    if ((st = check_image(disp, stride, width, "disp"))) return st;
+    if (!points) return fail(SNX_ERR_ARG, "points is NULL");
+    if ((disp_dn || affine || normals) && out_stride < width)
+        return fail(SNX_ERR_ARG, "out_stride < width");
+    snx::StencilArgs a;
+    return fill_stencil(a, disp, stride, width, height, denoise->window / 2, normal->window / 2,
+                        need_f(denoise), need_g(normal), cam);
+}
+
+snx_status snx_oriented_point_cloud(const float *disp, int64_t stride, int32_t width,
+                                    int32_t height, const snx_camera *cam,
+                                    const snx_denoise_params *denoise,
+                                    const snx_normal_params *normal, const int32_t *labels,
+                                    int64_t label_stride, float *disp_dn, float *affine,
+                                    float *normals, int64_t out_stride, snx_point *points,
+                                    void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn,
+                                affine, normals, out_stride, points);
+    if (st || width == 0 || height == 0) return st;
+    if (labels && label_stride < width) return fail(SNX_ERR_ARG, "label_stride < width");
+    return fused_impl(disp, stride, width, height, cam, denoise, normal, labels, label_stride,
+                      disp_dn, affine, normals, out_stride, points, (hipStream_t)stream,
+                      "snx_oriented_point_cloud");
+}
+
+size_t snx_pipeline_workspace_size(int32_t width, int32_t height) { return ws_components(width, height); }
+
+snx_status snx_pipeline(const float *disp, int64_t stride, int32_t width, int32_t height,
+                        const snx_camera *cam, const snx_denoise_params *denoise,
+                        const snx_normal_params *normal, const snx_component_params *comp,
+                        float *disp_dn, float *affine, float *normals, int64_t out_stride,
+                        int32_t *labels, int64_t label_stride, int32_t *num_components,
+                        snx_point *points, void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st;
+    if ((st = check_comp(comp))) return st;
+    if ((st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn, affine,
+                          normals, out_stride, points)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (width == 0 || height == 0) {
+        if (!num_components) return SNX_OK;
+        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, s);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_pipeline");
+    }
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    if (!workspace || workspace_bytes < ws_components(width, height))
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_components(width, height));
+    st = components_impl(disp, stride, width, height, comp, labels, label_stride, num_components,
+                         workspace, workspace_bytes, s, "snx_pipeline");
+    if (st) return st;
+    return fused_impl(disp, stride, width, height, cam, denoise, normal, labels, label_stride,
+                      disp_dn, affine, normals, out_stride, points, s, "snx_pipeline");
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP translation units of libsnx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "snx.h"
+
+namespace snx {
+
+// A disparity sample is valid iff finite and > 0.  Inside the kernels invalid
+// samples are stored as 0.0f, so "valid" reduces to "> 0".
+__host__ __device__ inline bool valid_disp(float d) { return d > 0.0f && d < INFINITY; }
+
+// Output tile of the stencil kernel: TW columns (one wave's lanes) x th rows.
+constexpr int kTileW = 64;
+constexpr int kBlock = 256;
+constexpr int kMaxWindow = 63;
+
+struct StencilArgs {
+    const float *src;      // raw disparity (rf > 0) or denoised disparity (rf == 0)
+    int64_t ld_src;
+    int W, H;
+    int rf, rg;            // filter and gradient radii (0 = stage off)
+    int need_f, need_g;    // support thresholds
+    float fx, fy, b, u0, v0;
+    float *dn;             // denoised plane out (nullable)
+    int64_t ld_dn;
+    float *aff;            // a1, a2 planes (nullable)
+    float *nrm;            // nx, ny, nz planes (nullable)
+    int64_t ld_out, plane_out;
+    const int32_t *labels; // nullable
+    int64_t ld_lab;
+    snx_point *rec;        // nullable
+    int th;                // tile height
+};
+
+size_t stencil_lds_bytes(int rf, int rg, int th);
+int stencil_pick_tile_height(int rf, int rg);
+hipError_t launch_stencil(const StencilArgs &a, hipStream_t s);
+
+struct CclArgs {
+    const float *D;
+    int64_t ld;
+    int W, H;
+    double k_rel, t_abs;
+    int32_t *parent;       // W*H contiguous union-find array
+    int32_t *labels;       // output (may equal parent when ld_lab == W)
+    int64_t ld_lab;
+    int32_t *count;        // nullable
+};
+hipError_t launch_components(const CclArgs &a, hipStream_t s);
+
+struct CloudArgs {
+    const float *dn;
+    int64_t ld_dn;
+    const float *nrm;
+    int64_t ld_nrm, plane_nrm;
+    const int32_t *labels;
+    int64_t ld_lab;
+    int W, H;
+    float fx, fy, b, u0, v0;
+    snx_point *out;
+};
+hipError_t launch_point_cloud(const CloudArgs &a, hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s);
+
+// Point record from the denoised disparity and the normal (shared by the fused
+// stencil epilogue and the separate point-cloud kernel so both agree bitwise).
+__device__ inline snx_point make_point(int u, int v, float D, float nx, float ny,
+                                       float nz, int32_t label, float fx, float fy,
+                                       float b, float u0, float v0)
+{
+    snx_point p;
+    const bool def = valid_disp(D) && (nx == nx);
+    if (def) {
+        const float z = (fx * b) / D;
+        p.x = ((float)u - u0) * z / fx;
+        p.y = ((float)v - v0) * z / fy;
+        p.z = z;
+        p.nx = nx; p.ny = ny; p.nz = nz;
+    } else {
+        p.x = p.y = p.z = p.nx = p.ny = p.nz = __builtin_nanf("");
+    }
+    p.label = label;
+    p.flags = (def ? SNX_POINT_DEFINED : 0u) | (label >= 0 ? SNX_POINT_LABELLED : 0u);
+    return p;
+}
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Streaming 2 x 16-byte store of one record (records are written once, never
+// re-read by the path).
+__device__ inline void store_point(snx_point *dst, const snx_point &p)
+{
+    const v4f lo = {p.x, p.y, p.z, p.nx};
+    const v4f hi = {p.ny, p.nz, __int_as_float(p.label), __uint_as_float(p.flags)};
+    v4f *d4 = reinterpret_cast<v4f *>(dst);
+    __builtin_nontemporal_store(lo, d4);
+    __builtin_nontemporal_store(hi, d4 + 1);
+}
+
+}  // namespace snx

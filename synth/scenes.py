@@ -341,7 +341,7 @@ def road_scene(width=2048, height=1024, f=2260.0, baseline=0.22, sigma=0.75,
         m = (t < z) & (t >= z_min) & (t <= z_far)
         z[m] = t[m]
         nrm[m] = n[m] if n.ndim == 3 else n
-        patch[m] = pid
+        patch[m] = pid[m] if np.ndim(pid) == 2 else pid
 
     h_cam = rng.uniform(1.2, 1.7)
     tg, _ = _plane_depth(rays, np.array([0.0, -1.0, 0.0]), -h_cam)
@@ -363,7 +363,9 @@ def road_scene(width=2048, height=1024, f=2260.0, baseline=0.22, sigma=0.75,
         lo = np.array([cx - sx / 2, h_cam - sy, cz - sz / 2])
         hi = np.array([cx + sx / 2, h_cam, cz + sz / 2])
         tb, nb = _box_depth(rays, lo, hi)
-        put(tb, nb, 3 + k)
+        # one patch id per box face (faces meet at creases)
+        face = np.argmax(np.abs(nb), axis=-1) * 2 + (nb.sum(-1) > 0)
+        put(tb, nb, 3 + 6 * k + face)
     z = np.where(np.isfinite(z), z, np.nan)
     with np.errstate(divide="ignore", invalid="ignore"):
         clean = cam.fx * cam.baseline / z

@@ -1,0 +1,131 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snx.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(snx_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2504_15121_amd import _lib
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) == 11
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2504_15121_amd import _lib
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_status_strings(lib):
+    assert lib.snx_status_string(0) == b"SNX_OK"
+    assert lib.snx_status_string(3) == b"SNX_ERR_WORKSPACE"
+    assert lib.snx_version() >= 100
+
+
+def test_workspace_sizes(lib):
+    assert lib.snx_components_workspace_size(640, 480) == 256 + 640 * 480 * 4
+    assert lib.snx_pipeline_workspace_size(1920, 1080) >= 1920 * 1080 * 4
+    assert lib.snx_components_workspace_size(1 << 16, 1 << 16) == 0   # too large
+
+
+FAKE = C.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def _dn(window=3, mode=0):
+    from paper_2504_15121_amd._lib import snx_denoise_params
+    return snx_denoise_params(window, 0, mode, 0, None)
+
+
+def _cam(fx=500.0, b=0.1):
+    from paper_2504_15121_amd._lib import snx_camera
+    return snx_camera(fx, fx, b, 10.0, 10.0)
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(disp=None), 1),
+    (dict(stride=10), 1),
+    (dict(window=4), 1),
+    (dict(window=0), 1),
+    (dict(window=65), 2),
+    (dict(mode=1), 2),
+    (dict(w=-1), 1),
+    (dict(w=70000, h=70000), 1),
+])
+def test_denoise_validation(lib, args, status):
+    p = _dn(args.get("window", 3), args.get("mode", 0))
+    disp = args.get("disp", FAKE)
+    st = lib.snx_denoise(disp, args.get("stride", 64), FAKE, 64, args.get("w", 64),
+                         args.get("h", 8), C.byref(p), None)
+    assert st == status
+    assert lib.snx_last_error() != b""
+
+
+def test_empty_calls_are_ok(lib):
+    p = _dn()
+    assert lib.snx_denoise(None, 0, None, 0, 0, 5, C.byref(p), None) == 0
+    assert lib.snx_denoise(None, 0, None, 0, 7, 0, C.byref(p), None) == 0
+
+
+def test_affine_normals_validation(lib):
+    from paper_2504_15121_amd._lib import snx_normal_params
+    ok = snx_normal_params(9, 0)
+    cam = _cam()
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(snx_normal_params(1, 0)),
+                                  FAKE, FAKE, 64, None) == 1
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(_cam(fx=-1.0)), C.byref(ok),
+                                  FAKE, FAKE, 64, None) == 1
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(_cam(b=float("nan"))), C.byref(ok),
+                                  FAKE, FAKE, 64, None) == 1
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(ok),
+                                  None, None, 64, None) == 1
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(ok),
+                                  FAKE, FAKE, 32, None) == 1
+    assert lib.snx_affine_normals(FAKE, 64, 64, 8, None, C.byref(ok), FAKE, FAKE, 64, None) == 1
+
+
+def test_components_validation(lib):
+    from paper_2504_15121_amd._lib import snx_component_params
+    p = snx_component_params(0.1, 1.0)
+    need = lib.snx_components_workspace_size(64, 8)
+    assert lib.snx_components(FAKE, 64, 64, 8, C.byref(p), FAKE, 64, None, None, need, None) == 3
+    assert lib.snx_components(FAKE, 64, 64, 8, C.byref(p), FAKE, 64, None, FAKE, need - 1,
+                              None) == 3
+    assert lib.snx_components(FAKE, 64, 64, 8, C.byref(snx_component_params(-0.1, 1.0)), FAKE,
+                              64, None, FAKE, need, None) == 1
+    assert lib.snx_components(FAKE, 64, 64, 8, C.byref(p), None, 64, None, FAKE, need, None) == 1
+    assert lib.snx_components(FAKE, 64, 64, 8, C.byref(p), FAKE, 63, None, FAKE, need, None) == 1
+
+
+def test_point_cloud_and_pipeline_validation(lib):
+    from paper_2504_15121_amd._lib import snx_component_params, snx_normal_params
+    cam = _cam()
+    assert lib.snx_point_cloud(FAKE, 64, FAKE, 64, None, 0, 64, 8, C.byref(cam), None, None) == 1
+    assert lib.snx_point_cloud(FAKE, 64, FAKE, 64, FAKE, 10, 64, 8, C.byref(cam), FAKE, None) == 1
+    dn, nr, cp = _dn(), snx_normal_params(9, 0), snx_component_params(0.1, 1.0)
+    need = lib.snx_pipeline_workspace_size(64, 8)
+    args = [FAKE, 64, 64, 8, C.byref(cam), C.byref(dn), C.byref(nr), C.byref(cp), None, None,
+            None, 64, FAKE, 64, None, FAKE, FAKE, need, None]
+    bad = list(args)
+    bad[15] = None                                  # points
+    assert lib.snx_pipeline(*bad) == 1
+    bad = list(args)
+    bad[17] = need - 4                              # workspace too small
+    assert lib.snx_pipeline(*bad) == 3
+    bad = list(args)
+    bad[6] = C.byref(snx_normal_params(2, 0))       # even window
+    assert lib.snx_pipeline(*bad) == 1
