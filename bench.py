@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the plain disparity -> oriented point cloud path.
+
+One step = the whole path on one 1920x1080 frame (seeded planes + quadrics
+scene, f = 1400 px, b = 0.2 m, sigma = 0.5 px, 8 % invalid in occlusion bands):
+snx_components (3 kernels) then snx_oriented_point_cloud (one fused kernel:
+3x3 LSQ filter, 9x9 masked LSQ gradients, A, normal, 32-byte point records).
+Inputs are resident in HBM before timing starts.  Steps rotate over several
+buffer sets (more than 512 MB in all) so that neither the input nor the output of
+a step is still in the 256 MB last-level cache from the previous use.
+
+Printed: ONE JSON line with value = Mpixel/s of the whole step, a roofline
+object for the dominant kernel (the fused stencil, timed with HIP events on the
+stream it runs on) and the FP64 CPU oracle's rate on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "normals Mpixel/s at 1 GPU (plain vs learned+batched); mean angular err (deg)"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per pixel of the fused kernel: raw disparity in (4), label in
+# (4), one 32-byte point record out
+FUSED_BYTES_PER_PX = 4 + 4 + 32
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--sets", type=int, default=8, help="rotating buffer sets")
+    ap.add_argument("--filter-window", type=int, default=3)
+    ap.add_argument("--normal-window", type=int, default=9)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 512 MiB device copy (reference for HBM counters)")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_src):
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_stencil_planes_quadrics_1920x1080_pmc.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m_sha or not m_b:
+        return None
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    return float(m_b.group(1)) if sha == m_sha.group(1) else None
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
+              "a multi-GPU run is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_15121_amd as snx
+    from synth import scenes
+
+    snx.load()
+    dev = torch.device("cuda:0")
+    sc = scenes.workload("planes_quadrics_1920x1080")
+    H, W = sc.disp.shape
+    f32 = lambda x: float(np.float32(x))
+    cam = scenes.Camera(f32(sc.cam.fx), f32(sc.cam.fy), f32(sc.cam.baseline), f32(sc.cam.u0),
+                        f32(sc.cam.v0))
+    nf, ng = args.filter_window, args.normal_window
+
+    d0 = torch.from_numpy(sc.disp).to(dev)
+    sets = []
+    for _ in range(args.sets):
+        sets.append(dict(
+            d=d0.clone(),
+            lab=torch.empty((H, W), dtype=torch.int32, device=dev),
+            cnt=torch.empty((1,), dtype=torch.int32, device=dev),
+            pts=torch.empty((H, W, 8), dtype=torch.float32, device=dev),
+            ws=torch.empty(snx.snx_components_workspace_size(W, H), dtype=torch.uint8,
+                           device=dev),
+        ))
+    set_bytes = sum(t.numel() * t.element_size() for t in sets[0].values())
+
+    def step(s, ev=None):
+        if ev is not None:
+            ev[0].record()
+        snx.snx_components(s["d"], s["lab"], s["ws"], num_components=s["cnt"])
+        if ev is not None:
+            ev[1].record()
+        snx.snx_oriented_point_cloud(s["d"], cam, s["pts"], labels=s["lab"], filter_window=nf,
+                                     normal_window=ng)
+        if ev is not None:
+            ev[2].record()
+
+    if args.copy_probe:
+        a = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for i in range(args.warmup):
+        step(sets[i % len(sets)])
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for i in range(args.steps):
+        step(sets[i % len(sets)], evs[i])
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    comp_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    fused_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    px = W * H
+    value = px / (ms_per_step * 1e-3) / 1e6
+
+    # accuracy of the produced normals against the generator's ground truth
+    s = sets[0]
+    pts = s["pts"].cpu().numpy()
+    n = pts[..., 3:6].astype(np.float64)
+    ok = np.isfinite(n[..., 0]) & np.isfinite(sc.normal[..., 0])
+    cr = np.linalg.norm(np.cross(n[ok], sc.normal[ok]), axis=-1)
+    dt = np.abs((n[ok] * sc.normal[ok]).sum(-1))
+    mean_err = float(np.degrees(np.arctan2(cr, dt)).mean())
+
+    achieved = FUSED_BYTES_PER_PX * px / (fused_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2504_15121_amd", "csrc",
+                                                 "stencil.hip"))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_stencil (snx_oriented_point_cloud)",
+                "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(fused_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle
+        oracle.load()
+        runs = []
+        oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)       # warm-up
+        t0 = time.perf_counter()
+        while len(runs) < 200 and (time.perf_counter() - t0 < 10.0 or len(runs) < 3):
+            t1 = time.perf_counter()
+            oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)
+            runs.append(time.perf_counter() - t1)
+        med = sorted(runs)[len(runs) // 2]
+        cpu = {"value": round(px / med / 1e6, 3), "unit": "Mpixel/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"full {W}x{H} frame, median of {len(runs)} runs "
+                         f"({sum(runs):.1f} s of CPU time)"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 accumulation)", "data": "synthetic",
+        "config": {"workload": "planes_quadrics_1920x1080", "width": W, "height": H,
+                   "path": "plain (snx_components + snx_oriented_point_cloud)",
+                   "filter_window": nf, "normal_window": ng, "k_rel": 0.1, "t_abs": 1.0,
+                   "rotating_sets": len(sets), "working_set_MB": round(set_bytes * len(sets) / 1e6)},
+        "stages_ms": {"components": round(comp_ms, 5), "fused_stencil": round(fused_ms, 5)},
+        "mean_angular_error_deg": round(mean_err, 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
