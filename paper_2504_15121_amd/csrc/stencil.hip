@@ -1,5 +1,5 @@
 // Fused LDS-tiled stencil: masked LSQ filter -> masked anchored LSQ slope ->
-// affine A -> normal -> point record, for one 64 x th output tile per workgroup.
+// affine A -> normal -> point record, for one 64 x TH output tile per workgroup.
 //
 // Both LSQ stages need, per pixel, the same separable window moments of a
 // validity-coded image v (v_i = D_i if valid else 0, m_i = [v_i > 0]):
@@ -9,13 +9,18 @@
 // column pass (over dy).  The three row mask moments are small integers packed
 // into one int32; the data moments are accumulated in FP64 (full-rate on CDNA4
 // vector ALUs once packed FP32 is off), so the uncentred sums lose nothing to
-// cancellation before the centring D_i - D_c is applied algebraically.
+// cancellation before the centring D_i - D_c is applied algebraically.  Every
+// determinant is an integer below 2^53 and is formed exactly in FP64.
 //
 // Filter (Sec. 3.2 LSQ with a constant column, solved by Cramer's rule on the
 // exact integer normal matrix) and slope (Sec. 3.2-3.3 eqs. convprep /
 // convprep2 with per-pixel alpha, beta, gamma as in the two-pass scheme of
 // Sec. 3.4) follow; then a1 = 1 - g_u, a2 = -g_v (Sec. 2 eq. affine_mtx with the
 // positive-disparity convention) and the normal of Sec. 3.1.
+//
+// The kernel is a template on the two radii so that the common windows are fully
+// unrolled with constant tap offsets and constant-divisor index arithmetic; a
+// runtime-radius instance serves every other window.
 #include "snx_internal.hpp"
 
 namespace snx {
@@ -33,7 +38,7 @@ __device__ inline void unpack(int p, int &c0, int &c1, int &c2)
 }
 
 struct Layout {
-    int R, inW, inH, dtW, dtH, rowW, rowH;
+    int R, inW, inH, dtW, dtH;
     size_t off_dt, off_c, off_s0, off_s1, bytes;
 };
 
@@ -48,14 +53,12 @@ __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
     L.dtW = kTileW + 2 * rg;
     L.dtH = th + 2 * rg;
     // the filter row pass covers inH rows x dtW columns, the slope row pass
-    // dtH rows x kTileW columns; one buffer serves both
-    L.rowW = L.dtW;
-    L.rowH = L.inH;
+    // dtH rows x kTileW columns; one set of buffers serves both
     size_t off = align_up(sizeof(float) * (size_t)L.inH * L.inW, 16);
     L.off_dt = off;
     if (rf > 0) off = align_up(off + sizeof(float) * (size_t)L.dtH * L.dtW, 16);
     L.off_c = off;
-    const size_t nrow = (size_t)L.rowH * L.rowW;
+    const size_t nrow = (size_t)L.inH * L.dtW;
     off = align_up(off + sizeof(int) * nrow, 16);
     L.off_s0 = off;
     off = align_up(off + sizeof(double) * nrow, 16);
@@ -65,13 +68,37 @@ __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
     return L;
 }
 
+// Row pass: packed mask moments and FP64 data moments of the window
+// p[0 .. 2r] (centre p[r]).
+template <int RC>
+__device__ inline void row_moments(const float *p, int r_rt, int &c, double &s0, double &s1)
+{
+    const int r = RC >= 0 ? RC : r_rt;
+    c = kC1Off * 64;
+    s0 = 0.0;
+    s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * r; ++k) {
+        const float v = p[k];
+        const int dx = k - r;
+        c += v > 0.0f ? pack_tap(dx) : 0;
+        const double dv = (double)v;
+        s0 += dv;
+        s1 += (double)dx * dv;
+    }
+}
+
+template <int RF, int RG, int TH>
 __global__ void __launch_bounds__(kBlock)
 k_stencil(StencilArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const Layout L = make_layout(a.rf, a.rg, a.th);
+    const int rf = RF >= 0 ? RF : a.rf;
+    const int rg = RG >= 0 ? RG : a.rg;
+    const int th = TH > 0 ? TH : a.th;
+    const Layout L = make_layout(rf, rg, th);
     float *sIn = reinterpret_cast<float *>(smem);
-    float *sDt = a.rf > 0 ? reinterpret_cast<float *>(smem + L.off_dt) : sIn;
+    float *sDt = rf > 0 ? reinterpret_cast<float *>(smem + L.off_dt) : sIn;
     int *sC = reinterpret_cast<int *>(smem + L.off_c);
     double *sS0 = reinterpret_cast<double *>(smem + L.off_s0);
     double *sS1 = reinterpret_cast<double *>(smem + L.off_s1);
@@ -81,7 +108,7 @@ k_stencil(StencilArgs a)
     const int wave = tid >> 6;
     constexpr int kWaves = kBlock / 64;
     const int x0 = blockIdx.x * kTileW;
-    const int y0 = blockIdx.y * a.th;
+    const int y0 = blockIdx.y * th;
     const int R = L.R;
 
     // ---- A: validity-coded input tile with halo R --------------------------
@@ -102,22 +129,13 @@ k_stencil(StencilArgs a)
     __syncthreads();
 
     // ---- B: filter (masked LSQ plane intercept) into sDt --------------------
-    if (a.rf > 0) {
-        const int rf = a.rf;
+    if (rf > 0) {
         // B1: row moments over dx for inH rows x dtW columns
         for (int e = tid; e < L.inH * L.dtW; e += kBlock) {
             const int ly = e / L.dtW, j = e - ly * L.dtW;
-            const float *p = sIn + ly * L.inW + j;   // window starts at column j
-            int c = kC1Off * 64;
-            double s0 = 0.0, s1 = 0.0;
-            for (int k = 0; k <= 2 * rf; ++k) {
-                const float v = p[k];
-                const int dx = k - rf;
-                c += v > 0.0f ? pack_tap(dx) : 0;
-                const double dv = (double)v;
-                s0 += dv;
-                s1 += (double)dx * dv;
-            }
+            int c;
+            double s0, s1;
+            row_moments<RF>(sIn + ly * L.inW + j, rf, c, s0, s1);
             sC[e] = c;
             sS0[e] = s0;
             sS1[e] = s1;
@@ -132,9 +150,10 @@ k_stencil(StencilArgs a)
             if (Dc > 0.0f) {
                 int N = 0, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
                 double R0 = 0.0, Rx = 0.0, Ry = 0.0;
+#pragma unroll
                 for (int k = 0; k <= 2 * rf; ++k) {
                     const int dy = k - rf;
-                    const int idx = (ty + k) * L.rowW + j;
+                    const int idx = e + k * L.dtW;
                     int c0, c1, c2;
                     unpack(sC[idx], c0, c1, c2);
                     N += c0; Sx += c1; Sy += dy * c0;
@@ -146,34 +165,35 @@ k_stencil(StencilArgs a)
                 }
                 double h = (double)Dc;
                 if (N >= a.need_f) {
-                    const long long m11 = (long long)Sxx * Syy - (long long)Sxy * Sxy;
-                    const long long det = (long long)N * m11
-                                        - (long long)Sx * ((long long)Sx * Syy - (long long)Sxy * Sy)
-                                        + (long long)Sy * ((long long)Sx * Sxy - (long long)Sxx * Sy);
-                    if (det != 0) {
+                    // exact integers below 2^53 for windows up to 63
+                    const double n = N, sx = Sx, sy = Sy, sxx = Sxx, sxy = Sxy, syy = Syy;
+                    const double m11 = sxx * syy - sxy * sxy;
+                    const double m12 = sx * syy - sxy * sy;
+                    const double m13 = sx * sxy - sxx * sy;
+                    const double det = n * m11 - sx * m12 + sy * m13;
+                    if (det != 0.0) {
                         const double dc = (double)Dc;
-                        const double r0 = R0 - (double)N * dc;
-                        const double r1 = Rx - (double)Sx * dc;
-                        const double r2 = Ry - (double)Sy * dc;
-                        const double num = r0 * (double)m11
-                                         - (double)Sx * (r1 * (double)Syy - (double)Sxy * r2)
-                                         + (double)Sy * (r1 * (double)Sxy - (double)Sxx * r2);
-                        h = dc + num / (double)det;
+                        const double r0 = R0 - n * dc;
+                        const double r1 = Rx - sx * dc;
+                        const double r2 = Ry - sy * dc;
+                        const double num = r0 * m11 - sx * (r1 * syy - sxy * r2)
+                                         + sy * (r1 * sxy - sxx * r2);
+                        h = dc + num / det;
                     }
                 }
                 outv = (float)h;
                 out = valid_disp(outv) ? outv : 0.0f;
             }
-            const int gx = x0 - a.rg + j, gy = y0 - a.rg + ty;
+            const int gx = x0 - rg + j, gy = y0 - rg + ty;
             const bool inimg = gx >= 0 && gx < a.W && gy >= 0 && gy < a.H;
             sDt[e] = inimg ? out : 0.0f;
-            if (a.dn && inimg && ty >= a.rg && ty < a.rg + a.th && j >= a.rg && j < a.rg + kTileW)
+            if (a.dn && inimg && ty >= rg && ty < rg + th && j >= rg && j < rg + kTileW)
                 a.dn[(int64_t)gy * a.ld_dn + gx] = outv;
         }
         __syncthreads();
     } else if (a.dn) {
         // identity filter: copy the (coded) centre values out
-        for (int e = tid; e < a.th * kTileW; e += kBlock) {
+        for (int e = tid; e < th * kTileW; e += kBlock) {
             const int ty = e >> 6, tx = e & 63;
             const int gx = x0 + tx, gy = y0 + ty;
             if (gx < a.W && gy < a.H) {
@@ -182,31 +202,22 @@ k_stencil(StencilArgs a)
             }
         }
     }
-    if (a.rg == 0) return;
+    if (rg == 0) return;
 
     // ---- C: anchored masked LSQ slope, A, normal, records --------------------
-    const int rg = a.rg;
     // C1: row moments over dx for dtH rows x 64 columns (centre column rg + tx)
     for (int e = tid; e < L.dtH * kTileW; e += kBlock) {
         const int ly = e >> 6, tx = e & 63;
-        const float *p = sDt + ly * L.dtW + tx;
-        int c = kC1Off * 64;
-        double s0 = 0.0, s1 = 0.0;
-        for (int k = 0; k <= 2 * rg; ++k) {
-            const float v = p[k];
-            const int dx = k - rg;
-            c += v > 0.0f ? pack_tap(dx) : 0;
-            const double dv = (double)v;
-            s0 += dv;
-            s1 += (double)dx * dv;
-        }
+        int c;
+        double s0, s1;
+        row_moments<RG>(sDt + ly * L.dtW + tx, rg, c, s0, s1);
         sC[e] = c;
         sS0[e] = s0;
         sS1[e] = s1;
     }
     __syncthreads();
     // C2: column moments, slope, outputs
-    for (int e = tid; e < a.th * kTileW; e += kBlock) {
+    for (int e = tid; e < th * kTileW; e += kBlock) {
         const int ty = e >> 6, tx = e & 63;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= a.W || gy >= a.H) continue;
@@ -215,9 +226,10 @@ k_stencil(StencilArgs a)
         if (Dc > 0.0f) {
             int N = 0, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
             double Px = 0.0, Py = 0.0;
+#pragma unroll
             for (int k = 0; k <= 2 * rg; ++k) {
                 const int dy = k - rg;
-                const int idx = (ty + k) * kTileW + tx;
+                const int idx = e + k * kTileW;
                 int c0, c1, c2;
                 unpack(sC[idx], c0, c1, c2);
                 N += c0; Sx += c1; Sy += dy * c0;
@@ -226,23 +238,26 @@ k_stencil(StencilArgs a)
                 Py += (double)dy * sS0[idx];
             }
             const int Ng = N - 1;   // the centre itself is not a neighbour
-            const long long det = (long long)Sxx * Syy - (long long)Sxy * Sxy;
-            if (Ng >= a.need_g && det > 0) {
+            const double al = Sxx, be = Sxy, ga = Syy;
+            const double det = al * ga - be * be;   // exact
+            if (Ng >= a.need_g && det > 0.0) {
                 const double dc = (double)Dc;
                 const double S1 = Px - (double)Sx * dc;
                 const double S2 = Py - (double)Sy * dc;
-                const double gu = ((double)Syy * S1 - (double)Sxy * S2) / (double)det;
-                const double gv = (-(double)Sxy * S1 + (double)Sxx * S2) / (double)det;
+                const double inv = 1.0 / det;
+                const double gu = (ga * S1 - be * S2) * inv;
+                const double gv = (al * S2 - be * S1) * inv;
                 a1 = (float)(1.0 - gu);
                 a2 = (float)(-gv);
-                const double mx = (double)a.fx * gu;
-                const double my = (double)a.fy * gv;
-                const double mz = dc - ((double)gx - (double)a.u0) * gu
-                                     - ((double)gy - (double)a.v0) * gv;
-                const double inv = -1.0 / sqrt(mx * mx + my * my + mz * mz);
-                nx = (float)(mx * inv);
-                ny = (float)(my * inv);
-                nz = (float)(mz * inv);
+                const double mxd = (double)a.fx * gu;
+                const double myd = (double)a.fy * gv;
+                const double mzd = dc - ((double)gx - (double)a.u0) * gu
+                                      - ((double)gy - (double)a.v0) * gv;
+                const float mx = (float)mxd, my = (float)myd, mz = (float)mzd;
+                const float s = -__frsqrt_rn(mx * mx + my * my + mz * mz);
+                nx = mx * s;
+                ny = my * s;
+                nz = mz * s;
             }
         }
         const int64_t o = (int64_t)gy * a.ld_out + gx;
@@ -264,15 +279,32 @@ k_stencil(StencilArgs a)
     }
 }
 
+using KernelFn = void (*)(StencilArgs);
+
+template <int RF, int RG, int TH>
+constexpr KernelFn kfn() { return &k_stencil<RF, RG, TH>; }
+
+// (rf, rg) pairs with a fully unrolled instance at tile height 16.
+struct Inst { int rf, rg; KernelFn fn; };
+constexpr Inst kInst[] = {
+    {1, 4, kfn<1, 4, 16>()}, {0, 4, kfn<0, 4, 16>()}, {1, 0, kfn<1, 0, 16>()},
+    {0, 1, kfn<0, 1, 16>()}, {0, 2, kfn<0, 2, 16>()}, {0, 3, kfn<0, 3, 16>()},
+    {0, 7, kfn<0, 7, 16>()}, {1, 1, kfn<1, 1, 16>()}, {1, 2, kfn<1, 2, 16>()},
+    {1, 3, kfn<1, 3, 16>()}, {1, 7, kfn<1, 7, 16>()}, {2, 4, kfn<2, 4, 16>()},
+    {2, 2, kfn<2, 2, 16>()}, {2, 7, kfn<2, 7, 16>()}, {2, 0, kfn<2, 0, 16>()},
+    {4, 0, kfn<4, 0, 16>()}, {4, 4, kfn<4, 4, 16>()},
+};
+
 }  // namespace
 
 size_t stencil_lds_bytes(int rf, int rg, int th) { return make_layout(rf, rg, th).bytes; }
 
+// Tallest tile whose LDS fits 64 KB (several workgroups per CU), else the
+// tallest that fits the 160 KB of one gfx950 CU.
 int stencil_pick_tile_height(int rf, int rg)
 {
-    const size_t budget = 64 * 1024;
     for (int th : {16, 8, 4}) {
-        if (stencil_lds_bytes(rf, rg, th) <= budget) return th;
+        if (stencil_lds_bytes(rf, rg, th) <= 64 * 1024) return th;
     }
     for (int th : {16, 8, 4, 2, 1}) {
         if (stencil_lds_bytes(rf, rg, th) <= 160 * 1024) return th;
@@ -284,7 +316,12 @@ hipError_t launch_stencil(const StencilArgs &a, hipStream_t s)
 {
     const size_t lds = stencil_lds_bytes(a.rf, a.rg, a.th);
     dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + a.th - 1) / a.th);
-    hipLaunchKernelGGL(k_stencil, grid, dim3(kBlock), lds, s, a);
+    KernelFn fn = &k_stencil<-1, -1, 0>;
+    if (a.th == 16) {
+        for (const Inst &i : kInst)
+            if (i.rf == a.rf && i.rg == a.rg) fn = i.fn;
+    }
+    hipLaunchKernelGGL(fn, grid, dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 

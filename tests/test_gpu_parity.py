@@ -238,3 +238,48 @@ def test_road_1024_closed_form_accuracy(oracle):
     ang = np.arctan2(np.linalg.norm(np.cross(n[inside], gt), axis=-1), (n[inside] * gt).sum(-1))
     # float32 quantisation of the input only (the FP64 oracle gives the same)
     assert np.percentile(ang, 99.9) < 1e-5, np.percentile(ang, 99.9)
+
+
+def _labels_gpu(D, pad):
+    snx = _snx()
+    H, W = D.shape
+    d = _to_dev(D, pad)
+    lab = torch.full((H, W + pad), -7, dtype=torch.int32, device=DEV)
+    cnt = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+    ws = torch.empty(snx.snx_components_workspace_size(W, H), dtype=torch.uint8, device=DEV)
+    snx.snx_components(d, lab[:, :W], ws, num_components=cnt)
+    torch.cuda.synchronize()
+    return lab[:, :W].cpu().numpy(), int(cnt.item())
+
+
+def _serpentine(H, W):
+    D = np.full((H, W), np.nan, np.float32)
+    for r in range(0, H, 4):
+        D[r:r + 2, :] = 10.0
+        c = W - 2 if (r // 4) % 2 == 0 else 0
+        D[r:r + 4, c:c + 2] = 10.0
+    return D
+
+
+@pytest.mark.parametrize("kind", ["serpentine", "checker", "levels", "stripes"])
+@pytest.mark.parametrize("pad", [0, 7])
+def test_components_adversarial(oracle, kind, pad):
+    print(f"case components {kind} pad={pad}", flush=True)
+    rng = np.random.default_rng(len(kind) + pad)
+    if kind == "serpentine":
+        D = _serpentine(998, 701)
+    elif kind == "checker":
+        v, u = np.mgrid[0:300, 0:517]
+        D = np.where((u + v) % 2 == 0, 10.0, 50.0).astype(np.float32)
+    elif kind == "levels":
+        D = rng.choice([5.0, 5.4, 6.0, 9.0, 9.9, 10.9, 20.0], size=(555, 777)).astype(np.float32)
+        D += rng.normal(0, 0.05, D.shape).astype(np.float32)
+        D[rng.random(D.shape) < 0.1] = np.nan
+    else:
+        v, u = np.mgrid[0:260, 0:640]
+        D = np.where((u // 64) % 2 == 0, 10.0, 40.0).astype(np.float32)
+        D[(v % 32) == 0] = np.nan
+    lab, cnt = _labels_gpu(D, pad)
+    ref, n = oracle.components(D, 0.1, 1.0)
+    assert np.array_equal(lab, ref), (lab != ref).sum()
+    assert cnt == n
