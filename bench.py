@@ -2,15 +2,17 @@
 """Throughput benchmark of the plain disparity -> oriented point cloud path.
 
 One step = the whole path on one 1920x1080 frame (seeded planes + quadrics
-scene, f = 1400 px, b = 0.2 m, sigma = 0.5 px, 8 % invalid in occlusion bands):
-snx_components (3 kernels) then snx_oriented_point_cloud (one fused kernel:
-3x3 LSQ filter, 9x9 masked LSQ gradients, A, normal, 32-byte point records).
+scene, f = 1400 px, b = 0.2 m, sigma = 0.5 px, 8 % invalid in occlusion bands),
+run as the two parts of snx_pipeline: part 1 (3x3 LSQ filter and per-tile
+component forests from one read of the disparity, then the seam unions) and
+part 2 (one fused kernel: 9x9 masked LSQ gradients, A, normal, label resolution,
+32-byte point records).
 Inputs are resident in HBM before timing starts.  Steps rotate over several
 buffer sets (more than 512 MB in all) so that neither the input nor the output of
 a step is still in the 256 MB last-level cache from the previous use.
 
 Printed: ONE JSON line with value = Mpixel/s of the whole step, a roofline
-object for the dominant kernel (the fused stencil, timed with HIP events on the
+object for the dominant kernel (the part-2 kernel, timed with HIP events on the
 stream it runs on) and the FP64 CPU oracle's rate on the host cores.
 """
 import argparse
@@ -26,9 +28,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "normals Mpixel/s at 1 GPU (plain vs learned+batched); mean angular err (deg)"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per pixel of the fused kernel: raw disparity in (4), label in
-# (4), one 32-byte point record out
-FUSED_BYTES_PER_PX = 4 + 4 + 32
+# algorithmic bytes per pixel of the part-2 kernel: filtered disparity in (4),
+# label forest in (4), final label out (4), one 32-byte point record out
+FUSED_BYTES_PER_PX = 4 + 4 + 4 + 32
 
 
 def parse():
@@ -91,7 +93,7 @@ def main():
             lab=torch.empty((H, W), dtype=torch.int32, device=dev),
             cnt=torch.empty((1,), dtype=torch.int32, device=dev),
             pts=torch.empty((H, W, 8), dtype=torch.float32, device=dev),
-            ws=torch.empty(snx.snx_components_workspace_size(W, H), dtype=torch.uint8,
+            ws=torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8,
                            device=dev),
         ))
     set_bytes = sum(t.numel() * t.element_size() for t in sets[0].values())
@@ -99,13 +101,17 @@ def main():
     def step(s, ev=None):
         if ev is not None:
             ev[0].record()
-        snx.snx_components(s["d"], s["lab"], s["ws"], num_components=s["cnt"])
+        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_FOREST,
+                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
         if ev is not None:
             ev[1].record()
-        snx.snx_oriented_point_cloud(s["d"], cam, s["pts"], labels=s["lab"], filter_window=nf,
-                                     normal_window=ng)
+        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_POINTS,
+                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
         if ev is not None:
             ev[2].record()
+
+    # pick tile heights for this frame size and these windows (set-up, untimed)
+    tiles = snx.snx_autotune(W, H, filter_window=nf, normal_window=ng)
 
     if args.copy_probe:
         a = torch.empty(128 << 20, dtype=torch.float32, device=dev)
@@ -148,7 +154,8 @@ def main():
                                                  "stencil.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_stencil (snx_oriented_point_cloud)",
+                "traffic": traffic,
+                "kernel": f"k_stencil<0,{ng // 2},{tiles[1]}> (snx_pipeline part 2)",
                 "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(fused_ms, 5)}
 
     cpu = None
@@ -174,10 +181,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 (f64 accumulation)", "data": "synthetic",
         "config": {"workload": "planes_quadrics_1920x1080", "width": W, "height": H,
-                   "path": "plain (snx_components + snx_oriented_point_cloud)",
+                   "path": "plain (snx_pipeline: part 1 forest+filter, part 2 points)",
                    "filter_window": nf, "normal_window": ng, "k_rel": 0.1, "t_abs": 1.0,
-                   "rotating_sets": len(sets), "working_set_MB": round(set_bytes * len(sets) / 1e6)},
-        "stages_ms": {"components": round(comp_ms, 5), "fused_stencil": round(fused_ms, 5)},
+                   "rotating_sets": len(sets), "working_set_MB": round(set_bytes * len(sets) / 1e6),
+                   "tile_heights": {"fused": tiles[0], "gradient": tiles[1]}},
+        "stages_ms": {"part1_forest_filter": round(comp_ms, 5), "part2_points": round(fused_ms, 5)},
         "mean_angular_error_deg": round(mean_err, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -189,13 +189,15 @@ snx_status snx_oriented_point_cloud(const float *disp, int64_t stride,
                                     void *stream);
 
 /* ---------------------------------------------------------------------------
- * snx_pipeline -- the whole path in the fewest passes: snx_components on the
- * raw disparity, then snx_oriented_point_cloud (one fused kernel for filter,
- * gradients, A, normal and point records).  Outputs are bit-identical to snx_denoise -> snx_affine_normals ->
- * snx_components -> snx_point_cloud with the same parameters.
+ * snx_pipeline -- the whole path in three kernels: one read of the raw disparity
+ * gives the filtered disparity and each tile's local component forest; tile
+ * seams are united; one fused kernel then computes gradients, A, normals,
+ * resolves the forest into final labels and writes the point records.  Outputs
+ * are bit-identical to snx_denoise -> snx_affine_normals -> snx_components ->
+ * snx_point_cloud with the same parameters.
  *   disp_dn, affine, normals: NULL or as in the separate calls (out_stride).
- *   labels [height x label_stride] required; num_components NULL or device int32.
- *   points: width * height records (required).
+ *   labels [height x label_stride] required (final labels on return);
+ *   num_components NULL or device int32; points: width * height records.
  *   workspace: at least snx_pipeline_workspace_size(width, height) bytes.
  * ------------------------------------------------------------------------- */
 size_t snx_pipeline_workspace_size(int32_t width, int32_t height);
@@ -212,6 +214,53 @@ snx_status snx_pipeline(const float *disp, int64_t stride,
                         snx_point *points,
                         void *workspace, size_t workspace_bytes,
                         void *stream);
+
+/* snx_pipeline split in two parts (for callers that interleave other work or
+ * time the parts): parts = SNX_PART_FOREST runs the filter, the local forests
+ * and the seam unions; parts = SNX_PART_POINTS runs the fused back kernel.
+ * Calling SNX_PART_FOREST then SNX_PART_POINTS on the same stream with the same
+ * arguments and workspace equals snx_pipeline (parts = SNX_PART_FOREST |
+ * SNX_PART_POINTS).  Between the two calls `labels` (or the workspace) holds a
+ * label forest, not final labels. */
+#define SNX_PART_FOREST 1
+#define SNX_PART_POINTS 2
+snx_status snx_pipeline_part(const float *disp, int64_t stride,
+                             int32_t width, int32_t height,
+                             const snx_camera *cam,
+                             const snx_denoise_params *denoise,
+                             const snx_normal_params *normal,
+                             const snx_component_params *comp,
+                             float *disp_dn, float *affine, float *normals,
+                             int64_t out_stride,
+                             int32_t *labels, int64_t label_stride,
+                             int32_t *num_components,
+                             snx_point *points,
+                             void *workspace, size_t workspace_bytes,
+                             int32_t parts, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * snx_autotune -- times the compiled tile heights of the stencil kernel for
+ * frames of width x height with these windows (the fused filter + gradient
+ * kernel, and when the filter window is > 1 also the gradient-only kernel that
+ * snx_pipeline's second part and snx_affine_normals use) on `stream`, and
+ * records the fastest for later calls in this process (and appends it to the
+ * file named by $SNX_AUTOTUNE_CACHE, which later processes read).  A set-up
+ * call: it allocates and frees temporary device memory and synchronizes the
+ * stream.  chosen: NULL or host int32[2] receiving the tile heights picked
+ * (fused, gradient-only); 0 means no compiled candidate (defaults apply).
+ * ------------------------------------------------------------------------- */
+snx_status snx_autotune(int32_t width, int32_t height,
+                        const snx_denoise_params *denoise,
+                        const snx_normal_params *normal,
+                        int32_t *chosen, void *stream);
+
+/* snx_tune_set -- pins (tile_height > 0) or clears (0) the tile height used for
+ * frames of this size class (floor(log2(width*height))) with these windows:
+ * filter_window 1 with normal_window n is the gradient-only kernel,
+ * normal_window 0 the filter-only kernel.  SNX_ERR_UNSUPPORTED if no kernel is
+ * compiled for that tile height.  Outputs never depend on the tile height. */
+snx_status snx_tune_set(int32_t width, int32_t height, int32_t filter_window,
+                        int32_t normal_window, int32_t tile_height);
 
 /* Status name ("SNX_OK", ...); never NULL. */
 const char *snx_status_string(snx_status status);

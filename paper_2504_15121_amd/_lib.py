@@ -68,6 +68,13 @@ SIGNATURES = {
                             C.POINTER(snx_denoise_params), C.POINTER(snx_normal_params),
                             C.POINTER(snx_component_params), _P, _P, _P, _I64, _P, _I64, _P, _P,
                             _P, _SZ, _P]),
+    "snx_pipeline_part": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                                 C.POINTER(snx_denoise_params), C.POINTER(snx_normal_params),
+                                 C.POINTER(snx_component_params), _P, _P, _P, _I64, _P, _I64,
+                                 _P, _P, _P, _SZ, _I32, _P]),
+    "snx_autotune": (_I32, [_I32, _I32, C.POINTER(snx_denoise_params),
+                            C.POINTER(snx_normal_params), _P, _P]),
+    "snx_tune_set": (_I32, [_I32, _I32, _I32, _I32, _I32]),
     "snx_status_string": (C.c_char_p, [_I32]),
     "snx_last_error": (C.c_char_p, []),
     "snx_version": (_I32, []),
@@ -224,9 +231,14 @@ def snx_pipeline_workspace_size(width, height):
     return int(load().snx_pipeline_workspace_size(width, height))
 
 
-def snx_pipeline(disp, cam, labels, points, workspace, num_components=None, disp_dn=None,
-                 affine=None, normals=None, filter_window=3, filter_min_support=0,
-                 normal_window=9, normal_min_support=0, k_rel=0.1, t_abs=1.0, stream=None):
+PART_FOREST = 1
+PART_POINTS = 2
+
+
+def snx_pipeline_part(disp, cam, labels, points, workspace, parts=3, num_components=None,
+                      disp_dn=None, affine=None, normals=None, filter_window=3,
+                      filter_min_support=0, normal_window=9, normal_min_support=0, k_rel=0.1,
+                      t_abs=1.0, stream=None):
     import torch
     H, W = disp.shape
     ld = _img(disp, torch.float32, "disp")
@@ -236,8 +248,32 @@ def snx_pipeline(disp, cam, labels, points, workspace, num_components=None, disp
     np_ = snx_normal_params(normal_window, normal_min_support)
     cp = snx_component_params(k_rel, t_abs)
     c = camera(cam)
-    _check(load().snx_pipeline(_ptr(disp), ld, W, H, C.byref(c), C.byref(dp), C.byref(np_),
-                               C.byref(cp), _ptr(disp_dn), _ptr(affine), _ptr(normals), out_ld,
-                               _ptr(labels), _img(labels, torch.int32, "labels"),
-                               _ptr(num_components), _ptr(points), _ptr(workspace),
-                               workspace.numel() * workspace.element_size(), _stream(stream)))
+    _check(load().snx_pipeline_part(_ptr(disp), ld, W, H, C.byref(c), C.byref(dp), C.byref(np_),
+                                    C.byref(cp), _ptr(disp_dn), _ptr(affine), _ptr(normals),
+                                    out_ld, _ptr(labels), _img(labels, torch.int32, "labels"),
+                                    _ptr(num_components), _ptr(points), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), int(parts),
+                                    _stream(stream)))
+
+
+def snx_pipeline(disp, cam, labels, points, workspace, num_components=None, disp_dn=None,
+                 affine=None, normals=None, filter_window=3, filter_min_support=0,
+                 normal_window=9, normal_min_support=0, k_rel=0.1, t_abs=1.0, stream=None):
+    snx_pipeline_part(disp, cam, labels, points, workspace, 3, num_components, disp_dn, affine,
+                      normals, filter_window, filter_min_support, normal_window,
+                      normal_min_support, k_rel, t_abs, stream)
+
+
+def snx_autotune(width, height, filter_window=3, normal_window=9, filter_min_support=0,
+                 normal_min_support=0, stream=None):
+    """Returns the tile heights chosen (fused, gradient-only)."""
+    dp = snx_denoise_params(filter_window, filter_min_support, 0, 0, None)
+    np_ = snx_normal_params(normal_window, normal_min_support)
+    out = (C.c_int32 * 2)()
+    _check(load().snx_autotune(width, height, C.byref(dp), C.byref(np_), C.cast(out, C.c_void_p),
+                               _stream(stream)))
+    return int(out[0]), int(out[1])
+
+
+def snx_tune_set(width, height, filter_window, normal_window, tile_height):
+    _check(load().snx_tune_set(width, height, filter_window, normal_window, tile_height))

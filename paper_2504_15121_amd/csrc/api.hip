@@ -101,7 +101,8 @@ snx_status fill_stencil(snx::StencilArgs &a, const float *src, int64_t ld, int32
     if (cam) {
         a.fx = cam->fx; a.fy = cam->fy; a.b = cam->baseline; a.u0 = cam->u0; a.v0 = cam->v0;
     }
-    a.th = snx::stencil_pick_tile_height(rf, rg);
+    a.th = snx::tuned_tile_height(rf, rg, w, h);
+    if (a.th == 0) a.th = snx::stencil_pick_tile_height(rf, rg);
     if (a.th == 0) return fail(SNX_ERR_UNSUPPORTED, "windows too large for one tile in LDS");
     return SNX_OK;
 }
@@ -266,7 +267,7 @@ static snx_status fused_impl(const float *disp, int64_t stride, int32_t width, i
     a.nrm = normals;
     a.ld_out = out_stride;
     a.plane_out = out_stride * (int64_t)height;
-    a.labels = labels;
+    a.labels = const_cast<int32_t *>(labels);   // read only: no forest to resolve
     a.ld_lab = label_stride;
     a.rec = points;
     hipError_t e = snx::launch_stencil(a, s);
@@ -310,7 +311,138 @@ snx_status snx_oriented_point_cloud(const float *disp, int64_t stride, int32_t w
                       "snx_oriented_point_cloud");
 }
 
-size_t snx_pipeline_workspace_size(int32_t width, int32_t height) { return ws_components(width, height); }
+static size_t plane_bytes(int32_t w, int32_t h)
+{
+    return ((size_t)w * (size_t)h * sizeof(float) + 255) / 256 * 256;
+}
+
+size_t snx_pipeline_workspace_size(int32_t width, int32_t height)
+{
+    if (!size_ok(width, height)) return 0;
+    return 256 + 2 * plane_bytes(width, height);
+}
+
+snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, int32_t height,
+                             const snx_camera *cam, const snx_denoise_params *denoise,
+                             const snx_normal_params *normal, const snx_component_params *comp,
+                             float *disp_dn, float *affine, float *normals, int64_t out_stride,
+                             int32_t *labels, int64_t label_stride, int32_t *num_components,
+                             snx_point *points, void *workspace, size_t workspace_bytes,
+                             int32_t parts, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (parts < 1 || parts > 3) return fail(SNX_ERR_ARG, "parts must be 1, 2 or 3");
+    snx_status st;
+    if ((st = check_comp(comp))) return st;
+    if ((st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn, affine,
+                          normals, out_stride, points)))
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (width == 0 || height == 0) {
+        if (!num_components || !(parts & 1)) return SNX_OK;
+        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, s);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_pipeline");
+    }
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    const size_t need = snx_pipeline_workspace_size(width, height);
+    if (!workspace || workspace_bytes < need)
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", need);
+
+    char *ws = static_cast<char *>(workspace);
+    int32_t *forest = label_stride == width ? labels : reinterpret_cast<int32_t *>(ws + 256);
+    float *dn = disp_dn ? disp_dn : reinterpret_cast<float *>(ws + 256 + plane_bytes(width, height));
+    const int64_t ld_dn = disp_dn ? out_stride : width;
+    const int rf = denoise->window / 2, rg = normal->window / 2;
+    const double k_rel = (double)comp->k_rel, t_abs = (double)comp->t_abs;
+    hipError_t e = hipSuccess;
+
+    if (parts & 1) {
+        // part 1: label forest and filtered disparity
+        snx::FrontArgs f;
+        f.D = disp;
+        f.ld = stride;
+        f.W = width;
+        f.H = height;
+        f.k_rel = k_rel;
+        f.t_abs = t_abs;
+        f.rf = rf <= 1 ? rf : 0;
+        f.need_f = need_f(denoise);
+        f.dn = rf <= 1 ? dn : nullptr;
+        f.ld_dn = ld_dn;
+        f.forest = forest;
+        f.count = num_components;
+        if ((e = snx::launch_front(f, s)) != hipSuccess) return hip_fail(e, "snx_pipeline");
+        if ((e = snx::launch_merge(disp, stride, width, height, k_rel, t_abs, forest, s)) !=
+            hipSuccess)
+            return hip_fail(e, "snx_pipeline");
+        if (rf > 1) {
+            snx::StencilArgs a;
+            if ((st = fill_stencil(a, disp, stride, width, height, rf, 0, need_f(denoise), 0,
+                                   nullptr)))
+                return st;
+            a.dn = dn;
+            a.ld_dn = ld_dn;
+            if ((e = snx::launch_stencil(a, s)) != hipSuccess) return hip_fail(e, "snx_pipeline");
+        }
+    }
+    if (parts & 2) {
+        // part 2: gradients, A, normals, label resolution, point records
+        snx::StencilArgs a;
+        if ((st = fill_stencil(a, dn, ld_dn, width, height, 0, rg, 0, need_g(normal), cam)))
+            return st;
+        a.aff = affine;
+        a.nrm = normals;
+        a.ld_out = out_stride;
+        a.plane_out = out_stride * (int64_t)height;
+        a.forest = forest;
+        a.labels = labels;
+        a.ld_lab = label_stride;
+        a.count = num_components;
+        a.rec = points;
+        if ((e = snx::launch_stencil(a, s)) != hipSuccess) return hip_fail(e, "snx_pipeline");
+    }
+    return SNX_OK;
+}
+
+snx_status snx_autotune(int32_t width, int32_t height, const snx_denoise_params *denoise,
+                        const snx_normal_params *normal, int32_t *chosen, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height) || width == 0 || height == 0)
+        return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st;
+    if ((st = check_denoise(denoise)) || (st = check_normal(normal))) return st;
+    const int rf = denoise->window / 2, rg = normal->window / 2;
+    int th_fused = 0, th_grad = 0;
+    hipError_t e = snx::autotune_stencil(rf, rg, need_f(denoise), need_g(normal), width, height,
+                                         (hipStream_t)stream, &th_fused);
+    if (e == hipSuccess && rf > 0)
+        e = snx::autotune_stencil(0, rg, 3, need_g(normal), width, height, (hipStream_t)stream,
+                                  &th_grad);
+    if (e != hipSuccess) return hip_fail(e, "snx_autotune");
+    if (chosen) {
+        chosen[0] = th_fused;
+        chosen[1] = rf > 0 ? th_grad : th_fused;
+    }
+    return SNX_OK;
+}
+
+snx_status snx_tune_set(int32_t width, int32_t height, int32_t filter_window,
+                        int32_t normal_window, int32_t tile_height)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height) || width == 0 || height == 0)
+        return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (filter_window < 1 || filter_window % 2 == 0 || normal_window < 0 ||
+        (normal_window > 0 && normal_window % 2 == 0) || filter_window > snx::kMaxWindow ||
+        normal_window > snx::kMaxWindow)
+        return fail(SNX_ERR_ARG, "bad windows %d, %d", filter_window, normal_window);
+    if (!snx::set_tile_height(filter_window / 2, normal_window / 2, width, height, tile_height))
+        return fail(SNX_ERR_UNSUPPORTED, "no compiled tile height %d for windows %d, %d",
+                    tile_height, filter_window, normal_window);
+    return SNX_OK;
+}
 
 snx_status snx_pipeline(const float *disp, int64_t stride, int32_t width, int32_t height,
                         const snx_camera *cam, const snx_denoise_params *denoise,
@@ -319,27 +451,9 @@ snx_status snx_pipeline(const float *disp, int64_t stride, int32_t width, int32_
                         int32_t *labels, int64_t label_stride, int32_t *num_components,
                         snx_point *points, void *workspace, size_t workspace_bytes, void *stream)
 {
-    g_err[0] = 0;
-    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
-    snx_status st;
-    if ((st = check_comp(comp))) return st;
-    if ((st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn, affine,
-                          normals, out_stride, points)))
-        return st;
-    hipStream_t s = (hipStream_t)stream;
-    if (width == 0 || height == 0) {
-        if (!num_components) return SNX_OK;
-        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, s);
-        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_pipeline");
-    }
-    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
-    if (!workspace || workspace_bytes < ws_components(width, height))
-        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_components(width, height));
-    st = components_impl(disp, stride, width, height, comp, labels, label_stride, num_components,
-                         workspace, workspace_bytes, s, "snx_pipeline");
-    if (st) return st;
-    return fused_impl(disp, stride, width, height, cam, denoise, normal, labels, label_stride,
-                      disp_dn, affine, normals, out_stride, points, s, "snx_pipeline");
+    return snx_pipeline_part(disp, stride, width, height, cam, denoise, normal, comp, disp_dn,
+                             affine, normals, out_stride, labels, label_stride, num_components,
+                             points, workspace, workspace_bytes, 3, stream);
 }
 
 }  // extern "C"

@@ -1,93 +1,52 @@
-// Connected surface components: union-find labelling on the GPU.
+// Connected surface components on the GPU (union-find; helpers in ccl.hpp).
 //
-// Edges join 4-neighbours whose raw disparities pass the pairwise covered-depth
-// predicate |D_p - D_q| <= max(t_abs, k_rel * min(D_p, D_q)) in binary64 (the
-// stopping rule of Sec. 3.4 applied between neighbours).  Labels are the
-// smallest linear index of each component, which the union-find produces by
-// always hooking the larger root under the smaller one (parent[x] <= x holds at
-// all times, so every root is the minimum of its tree).
-//
-//   k_ccl_local   one 64 x 32 tile per workgroup, one wave per row at a time
-//                 (lane = column): horizontal edges as a 64-bit ballot give the
-//                 row runs, whose first pixel is the initial root; vertical
-//                 edges are united in LDS (atomicMin hooking) except where the
-//                 edge to the left already connects the same two runs; each
-//                 pixel's global parent is the global index of its local root.
+//   k_front       one 64 x 32 tile per workgroup: the local forest of the tile
+//                 (ballot row runs + LDS union-find), written as the global
+//                 index of each pixel's local root; optionally the filter of the
+//                 same tile (window 1 or 3) from the same read of the disparity.
 //   k_ccl_merge   one thread per tile-seam pixel pair; a pair is skipped when
 //                 the previous pair along the seam is joined and both sides are
-//                 joined to it inside their tiles (so the union is implied);
-//                 the rest are united in the global parent array.
+//                 joined to it inside their tiles (so the union is implied); the
+//                 rest are united in the global forest with atomicMin hooking.
 //   k_ccl_flatten every pixel follows its parent chain to the root, writes its
 //                 own label and counts roots with a wave ballot.
 //
 // During the merge, parent loads bypass L1 and a hook that lost a race is
-// retried from the value the atomic returned.  The flatten runs after every hook
-// is done; there, a pixel's entry only changes to its root, so ordinary loads
-// that see an older value still lead to the right root.
-#include "snx_internal.hpp"
+// retried from the value the atomic returned.  After the merge a pixel's entry
+// only ever changes to its root, so ordinary loads that see an older value still
+// lead to the right root.
+#include "ccl.hpp"
+#include "lsq.hpp"
 
 namespace snx {
 namespace {
 
-constexpr int kCW = 64;    // tile width (one wave = one row of the tile)
-constexpr int kCH = 32;    // tile height
-constexpr int kCWaves = 4;
-
-__device__ inline bool joined(float p, float q, double k_rel, double t_abs)
-{
-#pragma clang fp contract(off)
-    const double a = (double)p, b = (double)q;
-    const double d = fabs(a - b);
-    const double t = fmax(t_abs, k_rel * fmin(a, b));
-    return d <= t;
-}
-
-__device__ inline bool edge(float p, float q, double k_rel, double t_abs)
-{
-    return valid_disp(p) && valid_disp(q) && joined(p, q, k_rel, t_abs);
-}
-
-__device__ inline int lds_find(const int *par, int x)
-{
-    int p = par[x];
-    while (p != x) {
-        x = p;
-        p = par[x];
-    }
-    return x;
-}
-
-__device__ inline void lds_union(int *par, int a, int b)
-{
-    while (true) {
-        a = lds_find(par, a);
-        b = lds_find(par, b);
-        if (a == b) return;
-        if (a < b) { const int t = a; a = b; b = t; }
-        const int old = atomicMin(&par[a], b);
-        if (old == a) return;
-        a = old;
-    }
-}
+constexpr int kFrontWaves = 4;
 
 // Loads that bypass the per-CU L1 (the merge runs concurrently with hooks done
 // by other CUs).
-__device__ inline int gload(const int32_t *p)
+__device__ __forceinline__ int gload(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline int g_find(const int32_t *par, int x)
+// Find with path halving: a non-root entry is pointed at its grandparent.  Only
+// roots are ever hooked and a non-root never becomes a root again, so the
+// halving cannot undo a concurrent hook; atomicMin keeps every entry
+// monotonically decreasing along its chain of ancestors.
+__device__ __forceinline__ int g_find(int32_t *par, int x)
 {
-    int p = gload(par + x);
-    while (p != x) {
-        x = p;
-        p = gload(par + x);
+    while (true) {
+        const int p = gload(par + x);
+        if (p == x) return x;
+        const int gp = gload(par + p);
+        if (gp == p) return p;
+        atomicMin(par + x, gp);
+        x = gp;
     }
-    return x;
 }
 
-__device__ inline void g_union(int32_t *par, int a, int b)
+__device__ __forceinline__ void g_union(int32_t *par, int a, int b)
 {
     while (true) {
         a = g_find(par, a);
@@ -100,68 +59,53 @@ __device__ inline void g_union(int32_t *par, int a, int b)
     }
 }
 
-// Root of x after every hook is done: parents only move to ancestors during the
-// flatten, so plain loads that see an older value still reach the root.
-__device__ inline int flat_find(const int32_t *par, int x)
+template <int RF>
+__global__ void __launch_bounds__(kFrontWaves * 64)
+k_front(FrontArgs a)
 {
-    int p = par[x];
-    while (p != x) {
-        x = p;
-        p = par[x];
-    }
-    return x;
-}
-
-// Highest set bit position at or below `lane` of the run-start mask: the start
-// of the run that contains `lane`.
-__device__ inline int run_start(unsigned long long starts, int lane)
-{
-    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    return 63 - __clzll(starts & upto);
-}
-
-__global__ void __launch_bounds__(kCWaves * 64)
-k_ccl_local(CclArgs a)
-{
-    __shared__ float sd[kCH * kCW];
+    constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
+    __shared__ float sIn[inH * inW];
     __shared__ int par[kCH * kCW];
     __shared__ unsigned long long hmask[kCH];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x0 = blockIdx.x * kCW, y0 = blockIdx.y * kCH;
-    const int gx = x0 + lane;
     if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
 
-    // rows: values, horizontal-edge ballots, run-start parents
-    for (int ly = wave; ly < kCH; ly += kCWaves) {
-        const int gy = y0 + ly;
-        float v = 0.0f;
-        if (gx < a.W && gy < a.H) {
-            const float d = a.D[(int64_t)gy * a.ld + gx];
-            v = valid_disp(d) ? d : 0.0f;
+    // issue every load of the tile before the first wait
+    constexpr int NT = inH * inW, NL = (NT + kFrontWaves * 64 - 1) / (kFrontWaves * 64);
+    float v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int e = threadIdx.x + k * kFrontWaves * 64;
+        const int ly = e / inW, lx = e - ly * inW;
+        const int gy = y0 - RF + ly, gx = x0 - RF + lx;
+        v[k] = 0.0f;
+        if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+            v[k] = __builtin_nontemporal_load(a.D + (int64_t)gy * a.ld + gx);
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        const int e = threadIdx.x + k * kFrontWaves * 64;
+        if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
+    }
+    __syncthreads();
+
+    const int gx = x0 + lane;
+    if (a.dn) {
+        for (int ly = wave; ly < kCH; ly += kFrontWaves) {
+            const int gy = y0 + ly;
+            if (gx >= a.W || gy >= a.H) continue;
+            const float *p = sIn + (ly + RF) * inW + lane + RF;
+            float out = __builtin_nanf("");
+            if (p[0] > 0.0f) out = RF == 1 ? filter3x3(p, inW, a.need_f) : p[0];
+            a.dn[(int64_t)gy * a.ld_dn + gx] = out;
         }
-        const float left = __shfl_up(v, 1);
-        const bool ok = v > 0.0f;
-        const bool h = ok && lane > 0 && left > 0.0f && joined(v, left, a.k_rel, a.t_abs);
-        const unsigned long long hb = __ballot(h);
-        const unsigned long long vb = __ballot(ok);
-        sd[ly * kCW + lane] = v;
-        par[ly * kCW + lane] = ok ? ly * kCW + run_start(vb & ~hb, lane) : -1;
-        if (lane == 0) hmask[ly] = hb;
     }
-    __syncthreads();
-    // vertical edges between row ly-1 and ly
-    for (int ly = 1 + wave; ly < kCH; ly += kCWaves) {
-        const float v = sd[ly * kCW + lane];
-        const float up = sd[(ly - 1) * kCW + lane];
-        const bool e = v > 0.0f && up > 0.0f && joined(v, up, a.k_rel, a.t_abs);
-        const unsigned long long eb = __ballot(e);
-        // the edge at lane-1 already joins the same two runs when both rows
-        // continue their run from lane-1 to lane
-        const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
-        if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);
-    }
-    __syncthreads();
-    for (int ly = wave; ly < kCH; ly += kCWaves) {
+
+    local_forest([&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; }, par, hmask, lane,
+                 wave, kFrontWaves, a.k_rel, a.t_abs);
+
+    for (int ly = wave; ly < kCH; ly += kFrontWaves) {
         const int gy = y0 + ly;
         if (gx >= a.W || gy >= a.H) continue;
         const int l = ly * kCW + lane;
@@ -170,7 +114,7 @@ k_ccl_local(CclArgs a)
             const int r = lds_find(par, l);
             g = (y0 + (r >> 6)) * a.W + x0 + (r & 63);
         }
-        a.parent[(int64_t)gy * a.W + gx] = g;
+        a.forest[(int64_t)gy * a.W + gx] = g;
     }
 }
 
@@ -178,47 +122,48 @@ k_ccl_local(CclArgs a)
 // per row y.  Horizontal seam s (between rows y-1 and y = (s+1)*kCH): thread per
 // column x.  Pair i is implied by pair i-1 along the same seam when pair i-1 is
 // joined and each side of pair i is joined to its side of pair i-1 (those edges
-// lie inside one tile and were united by k_ccl_local).
+// lie inside one tile and were united by the front kernel).
 __global__ void __launch_bounds__(256)
-k_ccl_merge(CclArgs a, int n_vseams, int n_hseams)
+k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs, int32_t *par,
+            int n_vseams, int n_hseams)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nv = (int64_t)n_vseams * a.H;
+    const int64_t nv = (int64_t)n_vseams * H;
     int p, q;
     if (i < nv) {
-        const int s = (int)(i / a.H), y = (int)(i - (int64_t)s * a.H);
+        const int s = (int)(i / H), y = (int)(i - (int64_t)s * H);
         const int x = (s + 1) * kCW;
-        const float *r = a.D + (int64_t)y * a.ld;
+        const float *r = D + (int64_t)y * ld;
         const float dp = r[x - 1], dq = r[x];
-        if (!edge(dp, dq, a.k_rel, a.t_abs)) return;
+        if (!edge(dp, dq, k_rel, t_abs)) return;
         if (y % kCH != 0) {
-            const float *u = r - a.ld;
+            const float *u = r - ld;
             const float up = u[x - 1], uq = u[x];
-            if (edge(up, uq, a.k_rel, a.t_abs) && edge(up, dp, a.k_rel, a.t_abs) &&
-                edge(uq, dq, a.k_rel, a.t_abs))
+            if (edge(up, uq, k_rel, t_abs) && edge(up, dp, k_rel, t_abs) &&
+                edge(uq, dq, k_rel, t_abs))
                 return;
         }
-        p = y * a.W + x - 1;
+        p = y * W + x - 1;
         q = p + 1;
     } else {
         const int64_t j = i - nv;
-        if (j >= (int64_t)n_hseams * a.W) return;
-        const int s = (int)(j / a.W), x = (int)(j - (int64_t)s * a.W);
+        if (j >= (int64_t)n_hseams * W) return;
+        const int s = (int)(j / W), x = (int)(j - (int64_t)s * W);
         const int y = (s + 1) * kCH;
-        const float *ra = a.D + (int64_t)(y - 1) * a.ld;
-        const float *rb = ra + a.ld;
+        const float *ra = D + (int64_t)(y - 1) * ld;
+        const float *rb = ra + ld;
         const float dp = ra[x], dq = rb[x];
-        if (!edge(dp, dq, a.k_rel, a.t_abs)) return;
+        if (!edge(dp, dq, k_rel, t_abs)) return;
         if (x % kCW != 0) {
             const float lp = ra[x - 1], lq = rb[x - 1];
-            if (edge(lp, lq, a.k_rel, a.t_abs) && edge(lp, dp, a.k_rel, a.t_abs) &&
-                edge(lq, dq, a.k_rel, a.t_abs))
+            if (edge(lp, lq, k_rel, t_abs) && edge(lp, dp, k_rel, t_abs) &&
+                edge(lq, dq, k_rel, t_abs))
                 return;
         }
-        p = (y - 1) * a.W + x;
-        q = p + a.W;
+        p = (y - 1) * W + x;
+        q = p + W;
     }
-    g_union(a.parent, p, q);
+    g_union(par, p, q);
 }
 
 __global__ void __launch_bounds__(256)
@@ -262,21 +207,50 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_front(const FrontArgs &a, hipStream_t s)
+{
+    const dim3 grid((a.W + kCW - 1) / kCW, (a.H + kCH - 1) / kCH);
+    if (a.rf == 0)
+        hipLaunchKernelGGL(k_front<0>, grid, dim3(kFrontWaves * 64), 0, s, a);
+    else if (a.rf == 1)
+        hipLaunchKernelGGL(k_front<1>, grid, dim3(kFrontWaves * 64), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
+                        int32_t *forest, hipStream_t s)
+{
+    const int tx = (W + kCW - 1) / kCW, ty = (H + kCH - 1) / kCH;
+    const int nv = tx - 1, nh = ty - 1;
+    const int64_t pairs = (int64_t)nv * H + (int64_t)nh * W;
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ccl_merge, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, D, ld,
+                       W, H, k_rel, t_abs, forest, nv, nh);
+    return hipGetLastError();
+}
+
 hipError_t launch_components(const CclArgs &a, hipStream_t s)
 {
-    const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
-    hipLaunchKernelGGL(k_ccl_local, dim3(tx, ty), dim3(kCWaves * 64), 0, s, a);
-    hipError_t e = hipGetLastError();
+    FrontArgs f;
+    f.D = a.D;
+    f.ld = a.ld;
+    f.W = a.W;
+    f.H = a.H;
+    f.k_rel = a.k_rel;
+    f.t_abs = a.t_abs;
+    f.rf = 0;
+    f.need_f = 3;
+    f.dn = nullptr;
+    f.ld_dn = 0;
+    f.forest = a.parent;
+    f.count = a.count;
+    hipError_t e = launch_front(f, s);
     if (e != hipSuccess) return e;
-    const int nv = tx - 1, nh = ty - 1;
-    const int64_t pairs = (int64_t)nv * a.H + (int64_t)nh * a.W;
-    if (pairs > 0) {
-        hipLaunchKernelGGL(k_ccl_merge, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s,
-                           a, nv, nh);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_ccl_flatten, dim3(tx, (a.H + 3) / 4), dim3(256), 0, s, a);
+    e = launch_merge(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.parent, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ccl_flatten, dim3((a.W + 63) / 64, (a.H + 3) / 4), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,109 @@
+// Union-find helpers for connected surface components, shared by the
+// components kernels and the fused front kernel.
+//
+// Edges join 4-neighbours whose raw disparities pass the pairwise covered-depth
+// predicate |D_p - D_q| <= max(t_abs, k_rel * min(D_p, D_q)) in binary64 (the
+// stopping rule of Sec. 3.4 applied between neighbours).  Labels are the
+// smallest linear index of each component: the union-find always hooks the
+// larger root under the smaller one, so parent[x] <= x holds at all times and
+// every root is the minimum of its tree.
+#pragma once
+
+#include "snx_internal.hpp"
+
+namespace snx {
+
+constexpr int kCW = 64;    // components tile width (one wave = one tile row)
+constexpr int kCH = 32;    // components tile height
+
+__device__ __forceinline__ bool joined(float p, float q, double k_rel, double t_abs)
+{
+#pragma clang fp contract(off)
+    const double a = (double)p, b = (double)q;
+    const double d = fabs(a - b);
+    const double t = fmax(t_abs, k_rel * fmin(a, b));
+    return d <= t;
+}
+
+__device__ __forceinline__ bool edge(float p, float q, double k_rel, double t_abs)
+{
+    return valid_disp(p) && valid_disp(q) && joined(p, q, k_rel, t_abs);
+}
+
+__device__ __forceinline__ int lds_find(const int *par, int x)
+{
+    int p = par[x];
+    while (p != x) {
+        x = p;
+        p = par[x];
+    }
+    return x;
+}
+
+__device__ __forceinline__ void lds_union(int *par, int a, int b)
+{
+    while (true) {
+        a = lds_find(par, a);
+        b = lds_find(par, b);
+        if (a == b) return;
+        if (a < b) { const int t = a; a = b; b = t; }
+        const int old = atomicMin(&par[a], b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+// Root of x once every hook is done: entries only change to their root, so
+// plain loads that see an older value still reach the root.
+__device__ __forceinline__ int flat_find(const int32_t *par, int x)
+{
+    int p = par[x];
+    while (p != x) {
+        x = p;
+        p = par[x];
+    }
+    return x;
+}
+
+// Highest set bit position at or below `lane` of the run-start mask: the start
+// of the run that contains `lane`.
+__device__ __forceinline__ int run_start(unsigned long long starts, int lane)
+{
+    const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    return 63 - __clzll(starts & upto);
+}
+
+// Local labelling of one kCW x kCH tile whose validity-coded values sit in LDS
+// at val(ly, lane) (0 = invalid).  Wave `wave` of `nwaves` takes every
+// nwaves-th row.  Horizontal edges come from a 64-bit ballot and give the row
+// runs (first pixel = initial root); vertical edges are united with atomicMin
+// hooking except where the edge at lane-1 already joins the same two runs.
+// On return (after a barrier) par[] holds a local forest over ly*kCW + lane.
+template <class Val>
+__device__ __forceinline__ void local_forest(Val val, int *par, unsigned long long *hmask,
+                                             int lane, int wave, int nwaves, double k_rel,
+                                             double t_abs)
+{
+    for (int ly = wave; ly < kCH; ly += nwaves) {
+        const float v = val(ly, lane);
+        const float left = __shfl_up(v, 1);
+        const bool ok = v > 0.0f;
+        const bool h = ok && lane > 0 && left > 0.0f && joined(v, left, k_rel, t_abs);
+        const unsigned long long hb = __ballot(h);
+        const unsigned long long vb = __ballot(ok);
+        par[ly * kCW + lane] = ok ? ly * kCW + run_start(vb & ~hb, lane) : -1;
+        if (lane == 0) hmask[ly] = hb;
+    }
+    __syncthreads();
+    for (int ly = 1 + wave; ly < kCH; ly += nwaves) {
+        const float v = val(ly, lane);
+        const float up = val(ly - 1, lane);
+        const bool e = v > 0.0f && up > 0.0f && joined(v, up, k_rel, t_abs);
+        const unsigned long long eb = __ballot(e);
+        const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
+        if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);
+    }
+    __syncthreads();
+}
+
+}  // namespace snx

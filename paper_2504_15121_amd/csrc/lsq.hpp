@@ -1,0 +1,234 @@
+// Separable masked window moments and the two LSQ solves, shared by every kernel
+// that filters or differentiates so that all of them produce bit-identical
+// results for the same input.
+//
+// For a validity-coded image v (v_i = D_i if valid else 0; m_i = [v_i > 0]) and a
+// window of offsets (dx, dy) around a centre, the LSQ steps need
+//     mask moments   N = sum m, Sx = sum m dx, Sy = sum m dy,
+//                    Sxx = sum m dx^2, Sxy = sum m dx dy, Syy = sum m dy^2
+//     data moments   R0 = sum v, Rx = sum dx v, Ry = sum dy v
+// A row pass sums over dx for every row; a column pass sums the row results
+// over dy.  Row mask moments are accumulated as one packed int32 per tap and
+// re-packed for the column pass; data moments are FP64 (uncentred sums in FP64
+// lose nothing that matters before D_c is subtracted algebraically).
+#pragma once
+
+#include "snx_internal.hpp"
+
+namespace snx {
+
+// Row-pass packing: c0 in bits 0..5, (c1 + 512) in bits 6..15, c2 in bits
+// 16..30 -- exact for windows up to 63.
+constexpr int kRowOff = 512;
+__device__ __forceinline__ int row_tap(int dx) { return 1 + dx * 64 + dx * dx * 65536; }
+
+// Column-pass packing of one row result: A = c0 + (c1 + kColOff) * 2^16, B = c2.
+// Summing A, dy*A and dy^2*A over the window then yields
+//   sum A       = N  + (Sx + kColOff * rows) * 2^16
+//   sum dy A    = Sy + Sxy * 2^16               (sum of dy over the window is 0)
+//   sum dy^2 A  = Syy (low 16 bits)
+// which is exact while N, Sx + kColOff*rows, Syy < 2^16 and |Sy|, |Sxy| < 2^15:
+// true for windows up to 21 (kPackedMaxR = 10).
+constexpr int kColOff = 512;
+constexpr int kPackedMaxR = 10;
+
+struct RowMom {
+    int a;        // packed c0 / c1 (column format) or raw row packing
+    int b;        // c2
+    double s0;    // sum v
+    double s1;    // sum dx v
+};
+
+// Row moments of the window p[0 .. 2r] (centre p[r]).
+template <int RC>
+__device__ __forceinline__ RowMom row_moments(const float *p, int r_rt)
+{
+    const int r = RC >= 0 ? RC : r_rt;
+    int c = kRowOff * 64;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * r; ++k) {
+        const float v = p[k];
+        const int dx = k - r;
+        c += v > 0.0f ? row_tap(dx) : 0;
+        const double dv = (double)v;
+        s0 += dv;
+        s1 += (double)dx * dv;
+    }
+    const int c0 = c & 63;
+    const int c1 = ((c >> 6) & 1023) - kRowOff;
+    const int c2 = c >> 16;
+    RowMom m;
+    m.a = c0 + (c1 + kColOff) * 65536;
+    m.b = c2;
+    m.s0 = s0;
+    m.s1 = s1;
+    return m;
+}
+
+struct ColMom {
+    int N, Sx, Sy, Sxx, Sxy, Syy;
+    double R0, Rx, Ry;
+};
+
+// Column pass over rows base[0], base[stride], ..., base[2r * stride] of the
+// row-moment arrays (a/b as int2, s0/s1 as double2).
+template <int RC, bool WANT_R0>
+__device__ __forceinline__ ColMom col_moments(const int2 *ab, const double2 *s, int stride,
+                                              int r_rt)
+{
+    const int r = RC >= 0 ? RC : r_rt;
+    ColMom o;
+    double R0 = 0.0, Rx = 0.0, Ry = 0.0;
+    if (RC >= 0 && RC <= kPackedMaxR) {
+        // unsigned: the packed sums wrap modulo 2^32 by design
+        unsigned SA = 0, YA = 0, YYA = 0, SB = 0;
+#pragma unroll
+        for (int k = 0; k <= 2 * r; ++k) {
+            const int dy = k - r;
+            const int2 w = ab[k * stride];
+            const double2 d = s[k * stride];
+            const unsigned wa = (unsigned)w.x;
+            SA += wa;
+            YA += (unsigned)dy * wa;
+            YYA += (unsigned)(dy * dy) * wa;
+            SB += (unsigned)w.y;
+            if (WANT_R0) R0 += d.x;
+            Rx += d.y;
+            Ry += (double)dy * d.x;
+        }
+        const int rows = 2 * r + 1;
+        o.N = (int)(SA & 0xffffu);
+        o.Sx = (int)(SA >> 16) - kColOff * rows;
+        o.Sy = (int)(short)(YA & 0xffffu);
+        o.Sxy = ((int)YA - o.Sy) >> 16;
+        o.Syy = (int)(YYA & 0xffffu);
+        o.Sxx = (int)SB;
+    } else {
+        int N = 0, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
+        for (int k = 0; k <= 2 * r; ++k) {
+            const int dy = k - r;
+            const int2 w = ab[k * stride];
+            const double2 d = s[k * stride];
+            const int c0 = w.x & 0xffff;
+            const int c1 = (w.x >> 16) - kColOff;
+            N += c0; Sx += c1; Sy += dy * c0;
+            Sxx += w.y; Sxy += dy * c1; Syy += dy * dy * c0;
+            if (WANT_R0) R0 += d.x;
+            Rx += d.y;
+            Ry += (double)dy * d.x;
+        }
+        o.N = N; o.Sx = Sx; o.Sy = Sy; o.Sxx = Sxx; o.Sxy = Sxy; o.Syy = Syy;
+    }
+    o.R0 = R0;
+    o.Rx = Rx;
+    o.Ry = Ry;
+    return o;
+}
+
+// 1/d for d >= 1 (an exact integer here): hardware reciprocal refined by two
+// Newton steps, accurate to a few ulp of FP64.
+__device__ __forceinline__ double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// Filter (LSQ plane intercept at the centre): pass-through when fewer than
+// need_f pixels are valid or the 3x3 normal matrix is singular.  Every
+// determinant term is an exact integer below 2^53 for windows up to 63.
+__device__ __forceinline__ float filter_solve(const ColMom &m, float Dc, int need_f)
+{
+    double h = (double)Dc;
+    if (m.N >= need_f) {
+        const double n = m.N, sx = m.Sx, sy = m.Sy, sxx = m.Sxx, sxy = m.Sxy, syy = m.Syy;
+        const double m11 = sxx * syy - sxy * sxy;
+        const double m12 = sx * syy - sxy * sy;
+        const double m13 = sx * sxy - sxx * sy;
+        const double det = n * m11 - sx * m12 + sy * m13;
+        if (det != 0.0) {
+            const double dc = (double)Dc;
+            const double r0 = m.R0 - n * dc;
+            const double r1 = m.Rx - sx * dc;
+            const double r2 = m.Ry - sy * dc;
+            const double num = r0 * m11 - sx * (r1 * syy - sxy * r2) + sy * (r1 * sxy - sxx * r2);
+            h = dc + num * recip(det);
+        }
+    }
+    return (float)h;
+}
+
+// Anchored slope (g_u, g_v) of Sec. 3.2-3.3 with the masked support of the
+// window excluding the centre; returns false where it is undefined.
+__device__ __forceinline__ bool slope_solve(const ColMom &m, float Dc, int need_g, double &gu,
+                                            double &gv)
+{
+    const double al = m.Sxx, be = m.Sxy, ga = m.Syy;
+    const double det = al * ga - be * be;   // exact
+    if (m.N - 1 < need_g || !(det > 0.0)) return false;
+    const double dc = (double)Dc;
+    const double S1 = m.Rx - (double)m.Sx * dc;
+    const double S2 = m.Ry - (double)m.Sy * dc;
+    const double inv = recip(det);
+    gu = (ga * S1 - be * S2) * inv;
+    gv = (al * S2 - be * S1) * inv;
+    return true;
+}
+
+// 3x3 mask moments packed in 5-bit fields: N | Sx+8 | Sy+8 | Sxx | Sxy+8 | Syy.
+constexpr int tap3(int dx, int dy)
+{
+    return 1 + dx * (1 << 5) + dy * (1 << 10) + dx * dx * (1 << 15) + dx * dy * (1 << 20) +
+           dy * dy * (1 << 25);
+}
+constexpr int kTap3Init = 8 * (1 << 5) + 8 * (1 << 10) + 8 * (1 << 20);
+
+// Direct 3x3 filter around the validity-coded value p[0] (row stride ld), for
+// a valid centre.  Every kernel that filters with n_f = 3 calls this.
+__device__ __forceinline__ float filter3x3(const float *p, int ld, int need_f)
+{
+    int c = kTap3Init;
+    double R0 = 0.0, Rx = 0.0, Ry = 0.0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const float v = p[dy * ld + dx];
+            c += v > 0.0f ? tap3(dx, dy) : 0;
+            const double dv = (double)v;
+            R0 += dv;
+            if (dx != 0) Rx += (double)dx * dv;
+            if (dy != 0) Ry += (double)dy * dv;
+        }
+    }
+    ColMom m;
+    m.N = c & 31;
+    m.Sx = ((c >> 5) & 31) - 8;
+    m.Sy = ((c >> 10) & 31) - 8;
+    m.Sxx = (c >> 15) & 31;
+    m.Sxy = ((c >> 20) & 31) - 8;
+    m.Syy = (c >> 25) & 31;
+    m.R0 = R0;
+    m.Rx = Rx;
+    m.Ry = Ry;
+    return filter_solve(m, p[0], need_f);
+}
+
+// Unit normal n = -m/|m| with m = (f_x g_u, f_y g_v, D - (u-u0) g_u - (v-v0) g_v).
+__device__ __forceinline__ void normal_from_slope(double gu, double gv, float Dc, int u, int v,
+                                                  float fx, float fy, float u0, float v0,
+                                                  float &nx, float &ny, float &nz)
+{
+    const double mxd = (double)fx * gu;
+    const double myd = (double)fy * gv;
+    const double mzd = (double)Dc - ((double)u - (double)u0) * gu - ((double)v - (double)v0) * gv;
+    const float mx = (float)mxd, my = (float)myd, mz = (float)mzd;
+    const float s = -__frsqrt_rn(mx * mx + my * my + mz * mz);
+    nx = mx * s;
+    ny = my * s;
+    nz = mz * s;
+}
+
+}  // namespace snx

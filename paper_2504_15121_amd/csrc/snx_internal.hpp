@@ -29,15 +29,41 @@ struct StencilArgs {
     float *aff;            // a1, a2 planes (nullable)
     float *nrm;            // nx, ny, nz planes (nullable)
     int64_t ld_out, plane_out;
-    const int32_t *labels; // nullable
+    int32_t *forest;       // nullable: label forest (W*H, linear indices) to resolve
+    int32_t *labels;       // nullable: final labels (input, or output when forest)
     int64_t ld_lab;
+    int32_t *count;        // nullable: roots are counted while resolving a forest
     snx_point *rec;        // nullable
     int th;                // tile height
 };
 
 size_t stencil_lds_bytes(int rf, int rg, int th);
 int stencil_pick_tile_height(int rf, int rg);
+bool stencil_has_instance(int rf, int rg, int th);
 hipError_t launch_stencil(const StencilArgs &a, hipStream_t s);
+// autotuned tile height for (rf, rg) at this frame size, 0 if not tuned
+int tuned_tile_height(int rf, int rg, int W, int H);
+// pin (th > 0, a compiled candidate) or clear (th == 0) the entry for this size class
+bool set_tile_height(int rf, int rg, int W, int H, int th);
+hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H, hipStream_t s,
+                            int *chosen);
+
+// Front of the pipeline: local components forest of each 64 x 32 tile plus the
+// filter (window 1 or 3) of the same tile, from one read of the raw disparity.
+struct FrontArgs {
+    const float *D;
+    int64_t ld;
+    int W, H;
+    double k_rel, t_abs;
+    int rf, need_f;
+    float *dn;             // nullable: filtered plane out
+    int64_t ld_dn;
+    int32_t *forest;       // W*H contiguous
+    int32_t *count;        // nullable: zeroed here
+};
+hipError_t launch_front(const FrontArgs &a, hipStream_t s);
+hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
+                        int32_t *forest, hipStream_t s);
 
 struct CclArgs {
     const float *D;

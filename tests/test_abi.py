@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 11
+    assert len(names) == 14
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -129,3 +129,30 @@ def test_point_cloud_and_pipeline_validation(lib):
     bad = list(args)
     bad[6] = C.byref(snx_normal_params(2, 0))       # even window
     assert lib.snx_pipeline(*bad) == 1
+
+
+def test_pipeline_part_validation(lib):
+    from paper_2504_15121_amd._lib import snx_component_params, snx_normal_params
+    cam = _cam()
+    dn, nr, cp = _dn(), snx_normal_params(9, 0), snx_component_params(0.1, 1.0)
+    need = lib.snx_pipeline_workspace_size(64, 8)
+    assert need >= 256 + 2 * 64 * 8 * 4
+    for parts in (0, 4, -1):
+        assert lib.snx_pipeline_part(FAKE, 64, 64, 8, C.byref(cam), C.byref(dn), C.byref(nr),
+                                     C.byref(cp), None, None, None, 64, FAKE, 64, None, FAKE,
+                                     FAKE, need, parts, None) == 1
+
+
+def test_autotune_validation(lib):
+    from paper_2504_15121_amd._lib import snx_normal_params
+    dn, nr = _dn(), snx_normal_params(9, 0)
+    assert lib.snx_autotune(0, 10, C.byref(dn), C.byref(nr), None, None) == 1
+    assert lib.snx_autotune(10, 10, C.byref(_dn(window=2)), C.byref(nr), None, None) == 1
+    assert lib.snx_autotune(10, 10, C.byref(dn), C.byref(snx_normal_params(65, 0)), None, None) == 2
+
+
+def test_tune_set(lib):
+    assert lib.snx_tune_set(640, 480, 1, 9, 32) == 0      # compiled candidate
+    assert lib.snx_tune_set(640, 480, 1, 9, 5) == 2       # not compiled
+    assert lib.snx_tune_set(640, 480, 2, 9, 16) == 1      # even window
+    assert lib.snx_tune_set(640, 480, 1, 9, 0) == 0       # clear

@@ -86,6 +86,35 @@ def run_fused(D, cam, nf, ng, k=0.1, t=1.0, pad=0, ms_g=0):
     return _host(o, H, W)
 
 
+def run_oriented(D, cam, nf, ng, k=0.1, t=1.0, pad=0, ms_g=0):
+    """snx_components then the fused filter+gradient+records call."""
+    snx = _snx()
+    H, W = D.shape
+    o = _alloc(H, W, pad)
+    d = _to_dev(D, pad)
+    snx.snx_components(d, o["lab"][:, :W], o["ws"], num_components=o["cnt"], k_rel=k, t_abs=t)
+    snx.snx_oriented_point_cloud(d, cam, o["pts"], labels=o["lab"][:, :W], disp_dn=o["dn"][:, :W],
+                                 affine=o["aff"], normals=o["nrm"], filter_window=nf,
+                                 normal_window=ng, normal_min_support=ms_g)
+    torch.cuda.synchronize()
+    return _host(o, H, W)
+
+
+def run_parts(D, cam, nf, ng, k=0.1, t=1.0, pad=0, ms_g=0):
+    """snx_pipeline_part(forest) then snx_pipeline_part(points)."""
+    snx = _snx()
+    H, W = D.shape
+    o = _alloc(H, W, pad)
+    d = _to_dev(D, pad)
+    for part in (snx.PART_FOREST, snx.PART_POINTS):
+        snx.snx_pipeline_part(d, cam, o["lab"][:, :W], o["pts"], o["ws"], parts=part,
+                              num_components=o["cnt"], disp_dn=o["dn"][:, :W], affine=o["aff"],
+                              normals=o["nrm"], filter_window=nf, normal_window=ng,
+                              normal_min_support=ms_g, k_rel=k, t_abs=t)
+    torch.cuda.synchronize()
+    return _host(o, H, W)
+
+
 def _host(o, H, W):
     return dict(dn=o["dn"][:, :W].cpu().numpy(), aff=o["aff"][:, :, :W].cpu().numpy(),
                 nrm=o["nrm"][:, :, :W].cpu().numpy(), lab=o["lab"][:, :W].cpu().numpy(),
@@ -153,6 +182,8 @@ def test_planes_640x480_separate_and_fused(oracle):
     print("max normal angle (rad)", ang)
     f = run_fused(sc.disp, cam, 3, 9)
     _same(g, f)
+    _same(g, run_oriented(sc.disp, cam, 3, 9))
+    _same(g, run_parts(sc.disp, cam, 3, 9))
 
 
 @pytest.mark.parametrize("H,W,nf,ng,nanfrac,pad", [
@@ -180,6 +211,7 @@ def test_sizes_and_edges(oracle, H, W, nf, ng, nanfrac, pad):
     check_parity(oracle, D, cam, nf, ng, g)
     f = run_fused(D, cam, nf, ng, pad=pad)
     _same(g, f)
+    _same(g, run_oriented(D, cam, nf, ng, pad=pad))
 
 
 def test_planes_quadrics_1920x1080_fused(oracle):
@@ -283,3 +315,29 @@ def test_components_adversarial(oracle, kind, pad):
     ref, n = oracle.components(D, 0.1, 1.0)
     assert np.array_equal(lab, ref), (lab != ref).sum()
     assert cnt == n
+
+
+def test_tile_heights_do_not_change_outputs():
+    """Every compiled tile height (and the autotuner's choice) gives bitwise
+    identical results."""
+    snx = _snx()
+    sc = scenes.planes_quadrics_scene(width=700, height=333, f=600.0, n_planes=12, n_spheres=4,
+                                      seed=31)
+    cam = _cam32(sc.cam)
+    H, W = sc.disp.shape
+    print("case tile heights", flush=True)
+    ref = run_fused(sc.disp, cam, 3, 9)
+    ref_o = run_oriented(sc.disp, cam, 3, 9)
+    for th in (8, 16, 32):
+        snx.snx_tune_set(W, H, 1, 9, th)
+        snx.snx_tune_set(W, H, 3, 9, th)
+        _same(ref, run_fused(sc.disp, cam, 3, 9))
+        _same(ref, run_oriented(sc.disp, cam, 3, 9))
+    snx.snx_tune_set(W, H, 1, 9, 0)
+    snx.snx_tune_set(W, H, 3, 9, 0)
+    chosen = snx.snx_autotune(W, H, 3, 9)
+    assert chosen[0] in (8, 16, 32) and chosen[1] in (8, 16, 32)
+    _same(ref, run_fused(sc.disp, cam, 3, 9))
+    _same(ref_o, run_oriented(sc.disp, cam, 3, 9))
+    snx.snx_tune_set(W, H, 1, 9, 0)
+    snx.snx_tune_set(W, H, 3, 9, 0)
