@@ -63,8 +63,11 @@ typedef struct snx_camera {
  * this is the box mean; n_f = 1 is the identity (the paper's unfiltered mode).
  * The centre value passes through unchanged when fewer than
  * max(3, min_support) pixels are valid or the 3x3 normal matrix is singular.
- * mode must be SNX_FILTER_LSQ; model must be NULL. */
+ * mode SNX_FILTER_LSQ: model must be NULL.  mode SNX_FILTER_CNN: the learned
+ * denoiser of snx_cnn_denoise replaces the filter (window/min_support unused);
+ * model points to an snx_cnn_model. */
 #define SNX_FILTER_LSQ 0
+#define SNX_FILTER_CNN 1   /* learned residual denoiser; model = const snx_cnn_model* */
 typedef struct snx_denoise_params {
     int32_t window;
     int32_t min_support;
@@ -261,6 +264,94 @@ snx_status snx_autotune(int32_t width, int32_t height,
  * compiled for that tile height.  Outputs never depend on the tile height. */
 snx_status snx_tune_set(int32_t width, int32_t height, int32_t filter_window,
                         int32_t normal_window, int32_t tile_height);
+
+/* ===========================================================================
+ * Learned residual denoiser (stands in for the LSQ filter; the paper notes the
+ * method is differentiable and convolution-like, Sec. 1).
+ *   mu = LSQ filter (window 3); x = [(D - mu)/s, valid] with s = 1 px;
+ *   six 3x3 convolutions 2->32, 4 x 32->32 (ReLU), 32->1, zero padding;
+ *   D~ = mu + s*y at valid pixels, NaN elsewhere.
+ * Weights and activations are bfloat16 with float32 accumulation (MFMA).
+ * Parameters: snx_cnn_param_count() floats, layer by layer W_k [Cout][Cin][3][3]
+ * then b_k.  `packed` holds snx_cnn_packed_bytes() bytes of bf16 weight layouts
+ * derived from the parameters by snx_cnn_pack (and by snx_cnn_train_step).
+ * ========================================================================= */
+typedef struct snx_cnn_model {
+    const float *params;    /* device, snx_cnn_param_count() floats */
+    const void *packed;     /* device, filled by snx_cnn_pack */
+    void *workspace;        /* device, >= snx_cnn_workspace_size(w, h, 1, 0) */
+    size_t workspace_bytes;
+} snx_cnn_model;
+
+int32_t snx_cnn_param_count(void);
+size_t snx_cnn_packed_bytes(void);
+/* Scratch for a batch of `batch` frames of width x height; training != 0 also
+ * keeps every activation and gradient for the backward pass. */
+size_t snx_cnn_workspace_size(int32_t width, int32_t height, int32_t batch, int32_t training);
+snx_status snx_cnn_pack(const float *params, void *packed, void *stream);
+
+/* Denoise one frame: disp [height x stride] -> out [height x out_stride]. */
+snx_status snx_cnn_denoise(const float *disp, int64_t stride, int32_t width, int32_t height,
+                           const snx_cnn_model *model, float *out, int64_t out_stride,
+                           void *stream);
+
+/* One training step on a batch of equally sized crops:
+ *   disp      device, batch x height x width (contiguous)
+ *   normals   device, batch x 3 x height x width ground-truth unit normals
+ *             (NaN where there is none)
+ *   cams      host, `batch` cameras (principal point relative to each crop);
+ *             batch <= 64
+ * Loss = mean over pixels with a defined normal (slope window normal_window)
+ * and a ground-truth normal of 1 - n . n_gt; its gradient flows through the
+ * normal, the slope, the residual and the network.  grad receives the
+ * parameter gradient.  step >= 1 then applies Adam (moments adam_m, adam_v,
+ * bias correction for this step number) to params and repacks `packed`;
+ * step == 0 only computes loss and grad.  loss_out: device double[2]
+ * (loss, number of pixels).  Deterministic: fixed-order reductions only. */
+snx_status snx_cnn_train_step(const float *disp, const float *normals, const snx_camera *cams,
+                              int32_t width, int32_t height, int32_t batch,
+                              int32_t normal_window, float *params, void *packed, float *grad,
+                              float *adam_m, float *adam_v, int32_t step, float lr,
+                              float beta1, float beta2, float eps, double *loss_out,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* ===========================================================================
+ * Batch plans: many frames of uneven size through the whole path (filter or
+ * learned filter, gradients, A, normals, components, point records) with one
+ * persistent launch per stage over a device-side (frame, tile) work list.  The
+ * first snx_plan_run on a (non-NULL) stream captures the launches in a
+ * hipGraph; later runs on that stream replay it.  The plan keeps the frame
+ * pointers: refill the input buffers in place between runs.  Outputs per frame
+ * are bit-identical to snx_pipeline with the same parameters.
+ * ========================================================================= */
+typedef struct snx_frame {
+    const float *disp;          /* raw disparity [height x stride]                  */
+    int64_t stride;
+    int32_t width, height;
+    snx_camera cam;
+    float *disp_dn;             /* NULL (plan-owned scratch) or [height x dn_stride]  */
+    int64_t dn_stride;
+    int32_t *labels;            /* [height x label_stride], final labels after a run */
+    int64_t label_stride;
+    snx_point *points;          /* width * height records                           */
+    int32_t *num_components;    /* NULL or device int32                             */
+} snx_frame;
+
+typedef struct snx_plan snx_plan;
+
+/* Validates every frame, picks the tile height (autotuned if snx_autotune ran
+ * for the largest frame's size class), allocates the device frame table and
+ * any per-frame scratch (a label forest when label_stride != width, the
+ * filtered plane when disp_dn is NULL).  The filter window must be 1 or 3, or
+ * mode SNX_FILTER_CNN with a model whose workspace fits the largest frame.
+ * A set-up call (allocates, synchronizes). */
+snx_status snx_plan_create(const snx_frame *frames, int32_t n,
+                           const snx_denoise_params *denoise,
+                           const snx_normal_params *normal,
+                           const snx_component_params *comp, snx_plan **plan);
+/* Runs every frame; asynchronous on `stream` (NULL: no graph capture). */
+snx_status snx_plan_run(snx_plan *plan, void *stream);
+snx_status snx_plan_destroy(snx_plan *plan);
 
 /* Status name ("SNX_OK", ...); never NULL. */
 const char *snx_status_string(snx_status status);

@@ -8,12 +8,16 @@ tensors into those calls.  Entry points (same names as the C functions):
     snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part, snx_components_workspace_size,
     snx_pipeline_workspace_size
 """
-from ._lib import (snx_autotune, snx_tune_set, POINT_DEFINED, POINT_LABELLED, SnxError, load, snx_affine_normals,
+from ._lib import (snx_autotune, snx_tune_set, snx_cnn_param_count, snx_cnn_packed_bytes,
+                   snx_cnn_workspace_size, snx_cnn_pack, snx_cnn_denoise, snx_cnn_train_step,
+                   cnn_model, Plan, FILTER_LSQ, FILTER_CNN, POINT_DEFINED, POINT_LABELLED, SnxError, load, snx_affine_normals,
                    snx_components, snx_components_workspace_size, snx_denoise,
                    snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part,
                    snx_pipeline_workspace_size, snx_point_cloud, PART_FOREST, PART_POINTS)
 
-__all__ = ["load", "snx_autotune", "snx_tune_set", "SnxError", "POINT_DEFINED", "POINT_LABELLED", "snx_denoise",
+__all__ = ["load", "snx_autotune", "snx_tune_set", "snx_cnn_param_count",
+           "snx_cnn_packed_bytes", "snx_cnn_workspace_size", "snx_cnn_pack", "snx_cnn_denoise",
+           "snx_cnn_train_step", "cnn_model", "Plan", "FILTER_LSQ", "FILTER_CNN", "SnxError", "POINT_DEFINED", "POINT_LABELLED", "snx_denoise",
            "snx_affine_normals", "snx_components", "snx_components_workspace_size",
            "snx_point_cloud", "snx_oriented_point_cloud", "snx_pipeline", "snx_pipeline_part",
            "snx_pipeline_workspace_size"]

@@ -37,6 +37,18 @@ class snx_denoise_params(C.Structure):
                 ("reserved", C.c_int32), ("model", C.c_void_p)]
 
 
+class snx_cnn_model(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("packed", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class snx_frame(C.Structure):
+    _fields_ = [("disp", C.c_void_p), ("stride", C.c_int64), ("width", C.c_int32),
+                ("height", C.c_int32), ("cam", snx_camera), ("disp_dn", C.c_void_p),
+                ("dn_stride", C.c_int64), ("labels", C.c_void_p), ("label_stride", C.c_int64),
+                ("points", C.c_void_p), ("num_components", C.c_void_p)]
+
+
 class snx_normal_params(C.Structure):
     _fields_ = [("window", C.c_int32), ("min_support", C.c_int32)]
 
@@ -75,6 +87,18 @@ SIGNATURES = {
     "snx_autotune": (_I32, [_I32, _I32, C.POINTER(snx_denoise_params),
                             C.POINTER(snx_normal_params), _P, _P]),
     "snx_tune_set": (_I32, [_I32, _I32, _I32, _I32, _I32]),
+    "snx_cnn_param_count": (_I32, []),
+    "snx_cnn_packed_bytes": (_SZ, []),
+    "snx_cnn_workspace_size": (_SZ, [_I32, _I32, _I32, _I32]),
+    "snx_cnn_pack": (_I32, [_P, _P, _P]),
+    "snx_cnn_denoise": (_I32, [_P, _I64, _I32, _I32, _P, _P, _I64, _P]),
+    "snx_cnn_train_step": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _I32,
+                                  C.c_float, C.c_float, C.c_float, C.c_float, _P, _P, _SZ, _P]),
+    "snx_plan_create": (_I32, [_P, _I32, C.POINTER(snx_denoise_params),
+                               C.POINTER(snx_normal_params), C.POINTER(snx_component_params),
+                               C.POINTER(C.c_void_p)]),
+    "snx_plan_run": (_I32, [_P, _P]),
+    "snx_plan_destroy": (_I32, [_P]),
     "snx_status_string": (C.c_char_p, [_I32]),
     "snx_last_error": (C.c_char_p, []),
     "snx_version": (_I32, []),
@@ -238,13 +262,15 @@ PART_POINTS = 2
 def snx_pipeline_part(disp, cam, labels, points, workspace, parts=3, num_components=None,
                       disp_dn=None, affine=None, normals=None, filter_window=3,
                       filter_min_support=0, normal_window=9, normal_min_support=0, k_rel=0.1,
-                      t_abs=1.0, stream=None):
+                      t_abs=1.0, stream=None, cnn=None):
+    """cnn: None (LSQ filter) or an snx_cnn_model (learned filter)."""
     import torch
     H, W = disp.shape
     ld = _img(disp, torch.float32, "disp")
     out_ld = _out_stride(disp_dn, affine, normals, H, W)
     _points(points, H, W)
-    dp = snx_denoise_params(filter_window, filter_min_support, 0, 0, None)
+    dp = snx_denoise_params(filter_window, filter_min_support, 0 if cnn is None else 1, 0,
+                            None if cnn is None else C.cast(C.pointer(cnn), C.c_void_p))
     np_ = snx_normal_params(normal_window, normal_min_support)
     cp = snx_component_params(k_rel, t_abs)
     c = camera(cam)
@@ -258,10 +284,11 @@ def snx_pipeline_part(disp, cam, labels, points, workspace, parts=3, num_compone
 
 def snx_pipeline(disp, cam, labels, points, workspace, num_components=None, disp_dn=None,
                  affine=None, normals=None, filter_window=3, filter_min_support=0,
-                 normal_window=9, normal_min_support=0, k_rel=0.1, t_abs=1.0, stream=None):
+                 normal_window=9, normal_min_support=0, k_rel=0.1, t_abs=1.0, stream=None,
+                 cnn=None):
     snx_pipeline_part(disp, cam, labels, points, workspace, 3, num_components, disp_dn, affine,
                       normals, filter_window, filter_min_support, normal_window,
-                      normal_min_support, k_rel, t_abs, stream)
+                      normal_min_support, k_rel, t_abs, stream, cnn)
 
 
 def snx_autotune(width, height, filter_window=3, normal_window=9, filter_min_support=0,
@@ -277,3 +304,97 @@ def snx_autotune(width, height, filter_window=3, normal_window=9, filter_min_sup
 
 def snx_tune_set(width, height, filter_window, normal_window, tile_height):
     _check(load().snx_tune_set(width, height, filter_window, normal_window, tile_height))
+
+
+FILTER_LSQ = 0
+FILTER_CNN = 1
+
+
+def snx_cnn_param_count():
+    return int(load().snx_cnn_param_count())
+
+
+def snx_cnn_packed_bytes():
+    return int(load().snx_cnn_packed_bytes())
+
+
+def snx_cnn_workspace_size(width, height, batch=1, training=False):
+    return int(load().snx_cnn_workspace_size(width, height, batch, int(bool(training))))
+
+
+def snx_cnn_pack(params, packed, stream=None):
+    _check(load().snx_cnn_pack(_ptr(params), _ptr(packed), _stream(stream)))
+
+
+def cnn_model(params, packed, workspace):
+    """snx_cnn_model for the C calls (keep the returned object alive)."""
+    return snx_cnn_model(params.data_ptr(), packed.data_ptr(), workspace.data_ptr(),
+                         workspace.numel() * workspace.element_size())
+
+
+def snx_cnn_denoise(disp, model, out, stream=None):
+    import torch
+    H, W = disp.shape
+    _check(load().snx_cnn_denoise(_ptr(disp), _img(disp, torch.float32, "disp"), W, H,
+                                  C.byref(model), _ptr(out), _img(out, torch.float32, "out"),
+                                  _stream(stream)))
+
+
+def snx_cnn_train_step(disp, normals, cams, params, packed, grad, adam_m, adam_v, step, lr,
+                       loss_out, workspace, normal_window=9, beta1=0.9, beta2=0.999, eps=1e-8,
+                       stream=None):
+    """disp (B, H, W) and normals (B, 3, H, W) device float32; cams: list of objects with
+    fx, fy, baseline, u0, v0; loss_out device float64[2]."""
+    B, H, W = disp.shape
+    carr = (snx_camera * B)(*[camera(c) for c in cams])
+    _check(load().snx_cnn_train_step(
+        _ptr(disp), _ptr(normals), C.cast(carr, C.c_void_p), W, H, B, normal_window,
+        _ptr(params), _ptr(packed), _ptr(grad), _ptr(adam_m), _ptr(adam_v), int(step),
+        float(lr), float(beta1), float(beta2), float(eps), _ptr(loss_out), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+class Plan:
+    """A batch plan over frames given as dicts of device tensors:
+    disp (H, W) f32, cam, labels (H, W) int32, points (H, W, 8) f32, optional
+    disp_dn (H, W) f32 and num_components (1,) int32.  Keep the tensors alive."""
+
+    def __init__(self, frames, filter_window=3, normal_window=9, k_rel=0.1, t_abs=1.0,
+                 cnn=None, normal_min_support=0):
+        import torch
+        arr = (snx_frame * len(frames))()
+        for i, f in enumerate(frames):
+            d = f["disp"]
+            H, W = d.shape
+            _points(f["points"], H, W)
+            dn = f.get("disp_dn")
+            arr[i] = snx_frame(d.data_ptr(), _img(d, torch.float32, "disp"), W, H,
+                               camera(f["cam"]), 0 if dn is None else dn.data_ptr(),
+                               0 if dn is None else _img(dn, torch.float32, "disp_dn"),
+                               f["labels"].data_ptr(), _img(f["labels"], torch.int32, "labels"),
+                               f["points"].data_ptr(),
+                               0 if f.get("num_components") is None else
+                               f["num_components"].data_ptr())
+        self._model = cnn
+        dp = snx_denoise_params(filter_window, 0, 0 if cnn is None else 1, 0,
+                                None if cnn is None else C.cast(C.pointer(cnn), C.c_void_p))
+        np_ = snx_normal_params(normal_window, normal_min_support)
+        cp = snx_component_params(k_rel, t_abs)
+        h = C.c_void_p()
+        _check(load().snx_plan_create(C.cast(arr, C.c_void_p), len(frames), C.byref(dp),
+                                      C.byref(np_), C.byref(cp), C.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        _check(load().snx_plan_run(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            load().snx_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -50,6 +50,13 @@ snx_status check_denoise(const snx_denoise_params *p)
         return fail(SNX_ERR_ARG, "filter window %d must be odd and >= 1", p->window);
     if (p->window > snx::kMaxWindow)
         return fail(SNX_ERR_UNSUPPORTED, "filter window %d > %d", p->window, snx::kMaxWindow);
+    if (p->mode == SNX_FILTER_CNN) {
+        const snx_cnn_model *m = static_cast<const snx_cnn_model *>(p->model);
+        if (!m || !m->params || !m->packed || !m->workspace)
+            return fail(SNX_ERR_MODEL, "CNN filter needs a model with params, packed weights "
+                                       "and workspace");
+        return SNX_OK;
+    }
     if (p->mode != SNX_FILTER_LSQ) return fail(SNX_ERR_UNSUPPORTED, "filter mode %d", p->mode);
     if (p->model) return fail(SNX_ERR_ARG, "LSQ filter takes no model");
     return SNX_OK;
@@ -109,6 +116,15 @@ snx_status fill_stencil(snx::StencilArgs &a, const float *src, int64_t ld, int32
 
 }  // namespace
 
+namespace snx {
+snx_status api_fail(snx_status st, const char *msg)
+{
+    g_err[0] = 0;
+    return fail(st, "%s", msg);
+}
+snx_status api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
+}  // namespace snx
+
 extern "C" {
 
 const char *snx_status_string(snx_status s)
@@ -139,6 +155,10 @@ snx_status snx_denoise(const float *disp, int64_t disp_stride, float *out, int64
     if (width == 0 || height == 0) return SNX_OK;
     if ((st = check_image(disp, disp_stride, width, "disp"))) return st;
     if ((st = check_image(out, out_stride, width, "out"))) return st;
+    if (params->mode == SNX_FILTER_CNN)
+        return snx_cnn_denoise(disp, disp_stride, width, height,
+                               static_cast<const snx_cnn_model *>(params->model), out, out_stride,
+                               stream);
     snx::StencilArgs a;
     if ((st = fill_stencil(a, disp, disp_stride, width, height, params->window / 2, 0,
                            need_f(params), 0, nullptr)))
@@ -305,6 +325,9 @@ snx_status snx_oriented_point_cloud(const float *disp, int64_t stride, int32_t w
     snx_status st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn,
                                 affine, normals, out_stride, points);
     if (st || width == 0 || height == 0) return st;
+    if (denoise->mode == SNX_FILTER_CNN)
+        return fail(SNX_ERR_UNSUPPORTED, "the fused call runs the LSQ filter only; use "
+                                         "snx_pipeline for the learned filter");
     if (labels && label_stride < width) return fail(SNX_ERR_ARG, "label_stride < width");
     return fused_impl(disp, stride, width, height, cam, denoise, normal, labels, label_stride,
                       disp_dn, affine, normals, out_stride, points, (hipStream_t)stream,
@@ -353,10 +376,17 @@ snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, i
     int32_t *forest = label_stride == width ? labels : reinterpret_cast<int32_t *>(ws + 256);
     float *dn = disp_dn ? disp_dn : reinterpret_cast<float *>(ws + 256 + plane_bytes(width, height));
     const int64_t ld_dn = disp_dn ? out_stride : width;
-    const int rf = denoise->window / 2, rg = normal->window / 2;
+    const bool cnn = denoise->mode == SNX_FILTER_CNN;
+    const int rf = cnn ? 0 : denoise->window / 2, rg = normal->window / 2;
     const double k_rel = (double)comp->k_rel, t_abs = (double)comp->t_abs;
     hipError_t e = hipSuccess;
 
+    if ((parts & 1) && cnn) {
+        // part 1 with the learned filter: the network, then the forest
+        st = snx_cnn_denoise(disp, stride, width, height,
+                             static_cast<const snx_cnn_model *>(denoise->model), dn, ld_dn, stream);
+        if (st) return st;
+    }
     if (parts & 1) {
         // part 1: label forest and filtered disparity
         snx::FrontArgs f;
@@ -368,7 +398,7 @@ snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, i
         f.t_abs = t_abs;
         f.rf = rf <= 1 ? rf : 0;
         f.need_f = need_f(denoise);
-        f.dn = rf <= 1 ? dn : nullptr;
+        f.dn = !cnn && rf <= 1 ? dn : nullptr;
         f.ld_dn = ld_dn;
         f.forest = forest;
         f.count = num_components;
@@ -413,7 +443,8 @@ snx_status snx_autotune(int32_t width, int32_t height, const snx_denoise_params 
         return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
     snx_status st;
     if ((st = check_denoise(denoise)) || (st = check_normal(normal))) return st;
-    const int rf = denoise->window / 2, rg = normal->window / 2;
+    const int rf = denoise->mode == SNX_FILTER_CNN ? 0 : denoise->window / 2;
+    const int rg = normal->window / 2;
     int th_fused = 0, th_grad = 0;
     hipError_t e = snx::autotune_stencil(rf, rg, need_f(denoise), need_g(normal), width, height,
                                          (hipStream_t)stream, &th_fused);

@@ -1,0 +1,262 @@
+// Batch plans: many frames of uneven size through the whole path with one
+// persistent launch per stage over a device-side (frame, tile) work list, the
+// launches captured once in a hipGraph and replayed on every run.
+//
+//   reset   zero the two work counters and every frame's component count
+//   [learned filter: the network per frame]
+//   front   persistent workgroups fetch (frame, tile) items: filter + local forest
+//   merge   one thread per tile-seam pair of every frame
+//   back    persistent workgroups fetch (frame, tile) items: gradients, A,
+//           normals, label resolution, point records
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "snx_internal.hpp"
+
+namespace snx {
+snx_status api_fail(snx_status st, const char *msg);
+snx_status api_hip_fail(hipError_t e, const char *where);
+}  // namespace snx
+
+struct snx_plan {
+    int n = 0;
+    bool cnn = false;
+    snx_cnn_model model{};
+    int rf = 0, rg = 0, th = 16;
+    std::vector<snx::BatchFrame> host;
+    snx::BatchFrame *d_frames = nullptr;
+    int *d_front_off = nullptr, *d_back_off = nullptr, *d_counters = nullptr;
+    int64_t *d_seam_off = nullptr;
+    int64_t seam_total = 0;
+    int grid_front = 1, grid_back = 1;
+    std::vector<void *> owned;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t captured_on = nullptr;
+};
+
+namespace {
+
+using snx::api_fail;
+using snx::api_hip_fail;
+
+void release(snx_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    for (void *q : p->owned) (void)hipFree(q);
+    (void)hipFree(p->d_frames);
+    (void)hipFree(p->d_front_off);
+    (void)hipFree(p->d_back_off);
+    (void)hipFree(p->d_seam_off);
+    (void)hipFree(p->d_counters);
+    delete p;
+}
+
+hipError_t enqueue(snx_plan *p, hipStream_t s)
+{
+    hipError_t e = snx::launch_batch_reset(p->d_counters, 2, p->d_frames, p->n, s);
+    if (e != hipSuccess) return e;
+    if (p->cnn) {
+        for (int i = 0; i < p->n; ++i) {
+            const snx::BatchFrame &f = p->host[i];
+            if (snx_cnn_denoise(f.front.D, f.front.ld, f.front.W, f.front.H, &p->model,
+                                const_cast<float *>(f.back.src), f.back.ld_src, s) != SNX_OK)
+                return hipErrorLaunchFailure;
+        }
+    }
+    if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->n, p->rf, p->d_counters,
+                                     p->grid_front, s)) != hipSuccess)
+        return e;
+    if ((e = snx::launch_batch_merge(p->d_frames, p->d_seam_off, p->n, p->seam_total, s)) !=
+        hipSuccess)
+        return e;
+    return snx::launch_batch_back(p->d_frames, p->d_back_off, p->n, p->rg, p->th,
+                                  p->d_counters + 1, p->grid_back, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise_params *dp,
+                           const snx_normal_params *np, const snx_component_params *cp,
+                           snx_plan **out)
+{
+    if (!out) return api_fail(SNX_ERR_ARG, "plan output pointer is NULL");
+    *out = nullptr;
+    if (!frames || n < 1 || !dp || !np || !cp) return api_fail(SNX_ERR_ARG, "NULL argument or n < 1");
+    const bool cnn = dp->mode == SNX_FILTER_CNN;
+    if (!cnn && dp->mode != SNX_FILTER_LSQ) return api_fail(SNX_ERR_UNSUPPORTED, "filter mode");
+    if (!cnn && (dp->window != 1 && dp->window != 3))
+        return api_fail(SNX_ERR_UNSUPPORTED, "batch plans filter with window 1 or 3");
+    if (cnn) {
+        const snx_cnn_model *m = static_cast<const snx_cnn_model *>(dp->model);
+        if (!m || !m->params || !m->packed || !m->workspace)
+            return api_fail(SNX_ERR_MODEL, "CNN filter needs a complete model");
+    }
+    if (np->window < 3 || np->window % 2 == 0 || np->window > snx::kMaxWindow)
+        return api_fail(SNX_ERR_ARG, "gradient window must be odd, 3..63");
+    if (!(isfinite(cp->k_rel) && cp->k_rel >= 0 && isfinite(cp->t_abs) && cp->t_abs >= 0))
+        return api_fail(SNX_ERR_ARG, "component thresholds");
+    const int rg = np->window / 2;
+    int maxW = 0, maxH = 0;
+    for (int i = 0; i < n; ++i) {
+        const snx_frame &f = frames[i];
+        if (f.width < 1 || f.height < 1 || (int64_t)f.width * f.height >= (1LL << 31))
+            return api_fail(SNX_ERR_ARG, "frame size");
+        if (!f.disp || f.stride < f.width || !f.labels || f.label_stride < f.width || !f.points)
+            return api_fail(SNX_ERR_ARG, "frame buffers or strides");
+        if (f.disp_dn && f.dn_stride < f.width) return api_fail(SNX_ERR_ARG, "dn_stride");
+        const snx_camera &c = f.cam;
+        if (!(isfinite(c.fx) && c.fx > 0 && isfinite(c.fy) && c.fy > 0 && isfinite(c.baseline) &&
+              c.baseline > 0 && isfinite(c.u0) && isfinite(c.v0)))
+            return api_fail(SNX_ERR_ARG, "frame camera");
+        if (cnn && snx_cnn_workspace_size(f.width, f.height, 1, 0) >
+                       static_cast<const snx_cnn_model *>(dp->model)->workspace_bytes)
+            return api_fail(SNX_ERR_WORKSPACE, "CNN workspace too small for a frame");
+        if ((int64_t)f.width * f.height > (int64_t)maxW * maxH) { maxW = f.width; maxH = f.height; }
+    }
+    int th = snx::tuned_tile_height(0, rg, maxW, maxH);
+    if (!snx::batch_has_instance(rg, th)) th = 16;
+    if (!snx::batch_has_instance(rg, th)) th = 8;
+    if (!snx::batch_has_instance(rg, th))
+        return api_fail(SNX_ERR_UNSUPPORTED, "no batched kernel for this gradient window");
+
+    snx_plan *p = new snx_plan;
+    p->n = n;
+    p->cnn = cnn;
+    if (cnn) p->model = *static_cast<const snx_cnn_model *>(dp->model);
+    p->rf = cnn ? 0 : dp->window / 2;
+    p->rg = rg;
+    p->th = th;
+    p->host.resize(n);
+    std::vector<int> foff(n + 1, 0), boff(n + 1, 0);
+    std::vector<int64_t> soff(n + 1, 0);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const snx_frame &f = frames[i];
+        int32_t *forest = f.labels;
+        if (f.label_stride != f.width) {
+            void *q = nullptr;
+            e = hipMalloc(&q, (size_t)f.width * f.height * 4);
+            if (e == hipSuccess) p->owned.push_back(q);
+            forest = static_cast<int32_t *>(q);
+        }
+        float *dn = f.disp_dn;
+        int64_t ld_dn = f.dn_stride;
+        if (!dn && e == hipSuccess) {
+            void *q = nullptr;
+            e = hipMalloc(&q, (size_t)f.width * f.height * 4);
+            if (e == hipSuccess) p->owned.push_back(q);
+            dn = static_cast<float *>(q);
+            ld_dn = f.width;
+        }
+        snx::BatchFrame &b = p->host[i];
+        memset(&b, 0, sizeof b);
+        b.front.D = f.disp;
+        b.front.ld = f.stride;
+        b.front.W = f.width;
+        b.front.H = f.height;
+        b.front.k_rel = cp->k_rel;
+        b.front.t_abs = cp->t_abs;
+        b.front.rf = p->rf;
+        b.front.need_f = dp->min_support > 3 ? dp->min_support : 3;
+        b.front.dn = cnn ? nullptr : dn;
+        b.front.ld_dn = ld_dn;
+        b.front.forest = forest;
+        b.front.count = f.num_components;
+        b.back.src = dn;
+        b.back.ld_src = ld_dn;
+        b.back.W = f.width;
+        b.back.H = f.height;
+        b.back.rf = 0;
+        b.back.rg = rg;
+        b.back.need_g = np->min_support > 0 ? np->min_support : (np->window * np->window + 1) / 2;
+        b.back.fx = f.cam.fx;
+        b.back.fy = f.cam.fy;
+        b.back.b = f.cam.baseline;
+        b.back.u0 = f.cam.u0;
+        b.back.v0 = f.cam.v0;
+        b.back.forest = forest;
+        b.back.labels = f.labels;
+        b.back.ld_lab = f.label_stride;
+        b.back.count = f.num_components;
+        b.back.rec = f.points;
+        b.back.th = th;
+        foff[i + 1] = foff[i] + snx::front_tiles(f.width, f.height);
+        boff[i + 1] = boff[i] + snx::back_tiles(f.width, f.height, th);
+        soff[i + 1] = soff[i] + snx::merge_pairs(f.width, f.height);
+    }
+    if (e == hipSuccess) e = hipMalloc(&p->d_frames, sizeof(snx::BatchFrame) * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_front_off, sizeof(int) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->d_back_off, sizeof(int) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->d_seam_off, sizeof(int64_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&p->d_counters, sizeof(int) * 2);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_frames, p->host.data(), sizeof(snx::BatchFrame) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_front_off, foff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_back_off, boff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_seam_off, soff.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        release(p);
+        return api_hip_fail(e, "snx_plan_create");
+    }
+    p->seam_total = soff[n];
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    // persistent grids: enough workgroups to fill every CU at full LDS occupancy
+    const int per_cu_back = (int)(160 * 1024 / snx::stencil_lds_bytes(0, rg, th));
+    p->grid_front = foff[n] < cus * 8 ? foff[n] : cus * 8;
+    p->grid_back = boff[n] < cus * per_cu_back ? boff[n] : cus * per_cu_back;
+    if (p->grid_back < 1) p->grid_back = 1;
+    *out = p;
+    return SNX_OK;
+}
+
+snx_status snx_plan_run(snx_plan *plan, void *stream)
+{
+    if (!plan) return api_fail(SNX_ERR_ARG, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (!s) {
+        // the legacy default stream cannot be captured: launch directly
+        e = enqueue(plan, s);
+        return e == hipSuccess ? SNX_OK : api_hip_fail(e, "snx_plan_run");
+    }
+    if (!plan->exec || plan->captured_on != s) {
+        if (plan->exec) { (void)hipGraphExecDestroy(plan->exec); plan->exec = nullptr; }
+        if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed)) != hipSuccess)
+            return api_hip_fail(e, "snx_plan_run capture");
+        const hipError_t le = enqueue(plan, s);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return api_hip_fail(le != hipSuccess ? le : e, "snx_plan_run capture");
+        }
+        plan->graph = g;
+        if ((e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+            return api_hip_fail(e, "snx_plan_run instantiate");
+        plan->captured_on = s;
+    }
+    e = hipGraphLaunch(plan->exec, s);
+    return e == hipSuccess ? SNX_OK : api_hip_fail(e, "snx_plan_run");
+}
+
+snx_status snx_plan_destroy(snx_plan *plan)
+{
+    release(plan);
+    return SNX_OK;
+}
+
+}  // extern "C"

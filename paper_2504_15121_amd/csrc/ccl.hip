@@ -60,16 +60,22 @@ __device__ __forceinline__ void g_union(int32_t *par, int a, int b)
 }
 
 template <int RF>
-__global__ void __launch_bounds__(kFrontWaves * 64)
-k_front(FrontArgs a)
+struct FrontSmem {
+    static constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
+    float sIn[inH * inW];
+    int par[kCH * kCW];
+    unsigned long long hmask[kCH];
+};
+
+// One 64 x 32 tile: filter (window 1 or 3) and local component forest.
+template <int RF>
+__device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by, FrontSmem<RF> &sm)
 {
-    constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
-    __shared__ float sIn[inH * inW];
-    __shared__ int par[kCH * kCW];
-    __shared__ unsigned long long hmask[kCH];
+    constexpr int inW = FrontSmem<RF>::inW, inH = FrontSmem<RF>::inH;
+    float *sIn = sm.sIn;
+    int *par = sm.par;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x0 = blockIdx.x * kCW, y0 = blockIdx.y * kCH;
-    if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
+    const int x0 = bx * kCW, y0 = by * kCH;
 
     // issue every load of the tile before the first wait
     constexpr int NT = inH * inW, NL = (NT + kFrontWaves * 64 - 1) / (kFrontWaves * 64);
@@ -102,8 +108,8 @@ k_front(FrontArgs a)
         }
     }
 
-    local_forest([&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; }, par, hmask, lane,
-                 wave, kFrontWaves, a.k_rel, a.t_abs);
+    local_forest([&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; }, par, sm.hmask,
+                 lane, wave, kFrontWaves, a.k_rel, a.t_abs);
 
     for (int ly = wave; ly < kCH; ly += kFrontWaves) {
         const int gy = y0 + ly;
@@ -118,16 +124,52 @@ k_front(FrontArgs a)
     }
 }
 
+template <int RF>
+__global__ void __launch_bounds__(kFrontWaves * 64)
+k_front(FrontArgs a)
+{
+    __shared__ FrontSmem<RF> sm;
+    if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
+    front_tile<RF>(a, blockIdx.x, blockIdx.y, sm);
+}
+
+// Persistent front over the (frame, tile) work list of a batch: workgroups
+// fetch items with an atomic counter until the list is exhausted.
+template <int RF>
+__global__ void __launch_bounds__(kFrontWaves * 64)
+k_front_batch(const BatchFrame *frames, const int *tile_off, int n, int *counter)
+{
+    __shared__ FrontSmem<RF> sm;
+    __shared__ int item;
+    const int total = tile_off[n];
+    while (true) {
+        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = item;
+        __syncthreads();
+        if (it >= total) break;
+        int lo = 0, hi = n - 1;            // frame f with tile_off[f] <= it < tile_off[f+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_off[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const FrontArgs a = frames[lo].front;
+        const int local = it - tile_off[lo];
+        const int tx = (a.W + kCW - 1) / kCW;
+        front_tile<RF>(a, local % tx, local / tx, sm);
+        __syncthreads();
+    }
+}
+
 // Seam pairs.  Vertical seam s (between columns x-1 and x = (s+1)*kCW): thread
 // per row y.  Horizontal seam s (between rows y-1 and y = (s+1)*kCH): thread per
 // column x.  Pair i is implied by pair i-1 along the same seam when pair i-1 is
 // joined and each side of pair i is joined to its side of pair i-1 (those edges
 // lie inside one tile and were united by the front kernel).
-__global__ void __launch_bounds__(256)
-k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs, int32_t *par,
-            int n_vseams, int n_hseams)
+__device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, int H, double k_rel,
+                                           double t_abs, int32_t *par, int n_vseams,
+                                           int n_hseams, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t nv = (int64_t)n_vseams * H;
     int p, q;
     if (i < nv) {
@@ -164,6 +206,38 @@ k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs
         q = p + W;
     }
     g_union(par, p, q);
+}
+
+__global__ void __launch_bounds__(256)
+k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs, int32_t *par,
+            int n_vseams, int n_hseams)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    merge_pair(D, ld, W, H, k_rel, t_abs, par, n_vseams, n_hseams, i);
+}
+
+// Seam pairs of every frame of a batch, one thread each.
+__global__ void __launch_bounds__(256)
+k_merge_batch(const BatchFrame *frames, const int64_t *seam_off, int n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= seam_off[n]) return;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seam_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    const FrontArgs &a = frames[lo].front;
+    const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
+    merge_pair(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.forest, tx - 1, ty - 1, i - seam_off[lo]);
+}
+
+// Work counters and per-frame component counts start at zero on every run.
+__global__ void k_batch_reset(int *counters, int n_counters, const BatchFrame *frames, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n_counters) counters[i] = 0;
+    if (i < n && frames[i].front.count) *frames[i].front.count = 0;
 }
 
 __global__ void __launch_bounds__(256)
@@ -216,6 +290,46 @@ hipError_t launch_front(const FrontArgs &a, hipStream_t s)
         hipLaunchKernelGGL(k_front<1>, grid, dim3(kFrontWaves * 64), 0, s, a);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int front_tiles(int W, int H) { return ((W + kCW - 1) / kCW) * ((H + kCH - 1) / kCH); }
+
+int64_t merge_pairs(int W, int H)
+{
+    const int tx = (W + kCW - 1) / kCW, ty = (H + kCH - 1) / kCH;
+    return (int64_t)(tx - 1) * H + (int64_t)(ty - 1) * W;
+}
+
+hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, int n, int rf,
+                              int *counter, int grid, hipStream_t s)
+{
+    if (rf == 0)
+        hipLaunchKernelGGL(k_front_batch<0>, dim3(grid), dim3(kFrontWaves * 64), 0, s, frames,
+                           tile_off, n, counter);
+    else if (rf == 1)
+        hipLaunchKernelGGL(k_front_batch<1>, dim3(grid), dim3(kFrontWaves * 64), 0, s, frames,
+                           tile_off, n, counter);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off, int n,
+                              int64_t total, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       frames, seam_off, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(int *counters, int n_counters, const BatchFrame *frames, int n,
+                              hipStream_t s)
+{
+    const int m = n > n_counters ? n : n_counters;
+    hipLaunchKernelGGL(k_batch_reset, dim3((m + 255) / 256), dim3(256), 0, s, counters,
+                       n_counters, frames, n);
     return hipGetLastError();
 }
 

@@ -65,6 +65,25 @@ hipError_t launch_front(const FrontArgs &a, hipStream_t s);
 hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
                         int32_t *forest, hipStream_t s);
 
+// One frame of a batch plan: the arguments of its front (filter + forest, and
+// the seam merge) and back (gradients, normals, labels, records) stages.
+struct BatchFrame {
+    FrontArgs front;
+    StencilArgs back;
+};
+int front_tiles(int W, int H);
+int64_t merge_pairs(int W, int H);
+hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, int n, int rf,
+                              int *counter, int grid, hipStream_t s);
+hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off, int n,
+                              int64_t total, hipStream_t s);
+hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, int n, int rg, int th,
+                             int *counter, int grid, hipStream_t s);
+hipError_t launch_batch_reset(int *counters, int n_counters, const BatchFrame *frames, int n,
+                              hipStream_t s);
+int back_tiles(int W, int H, int th);
+bool batch_has_instance(int rg, int th);
+
 struct CclArgs {
     const float *D;
     int64_t ld;

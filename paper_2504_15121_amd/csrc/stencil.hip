@@ -48,11 +48,11 @@ __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
     return L;
 }
 
+// One 64 x th output tile of the stencil.
 template <int RF, int RG, int TH>
-__global__ void __launch_bounds__(kBlock)
-k_stencil(StencilArgs a)
+__device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int by,
+                                             unsigned char *smem)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int rf = RF >= 0 ? RF : a.rf;
     const int rg = RG >= 0 ? RG : a.rg;
     const int th = TH > 0 ? TH : a.th;
@@ -63,8 +63,8 @@ k_stencil(StencilArgs a)
     double2 *sS = reinterpret_cast<double2 *>(smem + L.off_s);
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * kTileW;
-    const int y0 = blockIdx.y * th;
+    const int x0 = bx * kTileW;
+    const int y0 = by * th;
     const int R = L.R;
 
     // ---- A: validity-coded input tile with halo R --------------------------
@@ -228,6 +228,41 @@ k_stencil(StencilArgs a)
     }
 }
 
+template <int RF, int RG, int TH>
+__global__ void __launch_bounds__(kBlock)
+k_stencil(StencilArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    stencil_tile<RF, RG, TH>(a, blockIdx.x, blockIdx.y, smem);
+}
+
+// Persistent back stage over the (frame, tile) work list of a batch.
+template <int RG, int TH>
+__global__ void __launch_bounds__(kBlock)
+k_back_batch(const BatchFrame *frames, const int *tile_off, int n, int *counter)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int item;
+    const int total = tile_off[n];
+    while (true) {
+        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = item;
+        __syncthreads();
+        if (it >= total) break;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_off[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const StencilArgs a = frames[lo].back;
+        const int local = it - tile_off[lo];
+        const int tx = (a.W + kTileW - 1) / kTileW;
+        stencil_tile<0, RG, TH>(a, local % tx, local / tx, smem);
+        __syncthreads();
+    }
+}
+
 using KernelFn = void (*)(StencilArgs);
 
 template <int RF, int RG, int TH>
@@ -257,6 +292,36 @@ constexpr Inst kInst[] = {
 }  // namespace
 
 size_t stencil_lds_bytes(int rf, int rg, int th) { return make_layout(rf, rg, th).bytes; }
+
+int back_tiles(int W, int H, int th) { return ((W + kTileW - 1) / kTileW) * ((H + th - 1) / th); }
+
+using BatchFn = void (*)(const BatchFrame *, const int *, int, int *);
+struct BatchInst { int rg, th; BatchFn fn; };
+constexpr BatchInst kBatchInst[] = {
+    {1, 16, &k_back_batch<1, 16>}, {2, 16, &k_back_batch<2, 16>}, {3, 16, &k_back_batch<3, 16>},
+    {4, 8, &k_back_batch<4, 8>},   {4, 16, &k_back_batch<4, 16>}, {4, 32, &k_back_batch<4, 32>},
+    {7, 8, &k_back_batch<7, 8>},   {7, 16, &k_back_batch<7, 16>}, {10, 8, &k_back_batch<10, 8>},
+    {10, 16, &k_back_batch<10, 16>},
+};
+
+bool batch_has_instance(int rg, int th)
+{
+    for (const BatchInst &i : kBatchInst)
+        if (i.rg == rg && i.th == th) return true;
+    return false;
+}
+
+hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, int n, int rg, int th,
+                             int *counter, int grid, hipStream_t s)
+{
+    for (const BatchInst &i : kBatchInst)
+        if (i.rg == rg && i.th == th) {
+            hipLaunchKernelGGL(i.fn, dim3(grid), dim3(kBlock), stencil_lds_bytes(0, rg, th), s,
+                               frames, tile_off, n, counter);
+            return hipGetLastError();
+        }
+    return hipErrorInvalidValue;
+}
 
 bool stencil_has_instance(int rf, int rg, int th)
 {

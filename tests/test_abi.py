@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 14
+    assert len(names) == 23
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -62,7 +62,8 @@ def _cam(fx=500.0, b=0.1):
     (dict(window=4), 1),
     (dict(window=0), 1),
     (dict(window=65), 2),
-    (dict(mode=1), 2),
+    (dict(mode=1), 5),          # learned filter without a model
+    (dict(mode=2), 2),
     (dict(w=-1), 1),
     (dict(w=70000, h=70000), 1),
 ])
@@ -156,3 +157,41 @@ def test_tune_set(lib):
     assert lib.snx_tune_set(640, 480, 1, 9, 5) == 2       # not compiled
     assert lib.snx_tune_set(640, 480, 2, 9, 16) == 1      # even window
     assert lib.snx_tune_set(640, 480, 1, 9, 0) == 0       # clear
+
+
+def test_cnn_sizes_and_validation(lib):
+    assert lib.snx_cnn_param_count() == 37889
+    assert lib.snx_cnn_packed_bytes() == 2 * 80384
+    assert lib.snx_cnn_workspace_size(256, 256, 8, 1) > lib.snx_cnn_workspace_size(256, 256, 8, 0)
+    assert lib.snx_cnn_workspace_size(0, 256, 1, 0) == 0
+    assert lib.snx_cnn_pack(None, FAKE, None) == 1
+    assert lib.snx_cnn_denoise(FAKE, 64, 64, 8, None, FAKE, 64, None) == 5
+    from paper_2504_15121_amd._lib import snx_camera
+    cams = (snx_camera * 1)(snx_camera(500.0, 500.0, 0.1, 10.0, 10.0))
+    args = [FAKE, FAKE, C.cast(cams, C.c_void_p), 64, 64, 1, 9, FAKE, FAKE, FAKE, FAKE, FAKE, 1,
+            C.c_float(1e-3), C.c_float(0.9), C.c_float(0.999), C.c_float(1e-8), FAKE, FAKE, 10,
+            None]
+    assert lib.snx_cnn_train_step(*args) == 3          # workspace too small
+    bad = list(args); bad[6] = 4                         # even window
+    assert lib.snx_cnn_train_step(*bad) == 1
+    bad = list(args); bad[10] = None                     # Adam moments missing
+    assert lib.snx_cnn_train_step(*bad) == 1
+
+
+def test_plan_validation(lib):
+    from paper_2504_15121_amd._lib import (snx_component_params, snx_frame, snx_normal_params,
+                                           snx_camera)
+    out = C.c_void_p()
+    cp = snx_component_params(0.1, 1.0)
+    nr = snx_normal_params(9, 0)
+    fr = (snx_frame * 1)(snx_frame(0x1000, 64, 64, 8, snx_camera(500.0, 500.0, 0.1, 3.0, 3.0),
+                                   0, 0, 0x2000, 64, 0x3000, 0))
+    assert lib.snx_plan_create(C.cast(fr, C.c_void_p), 0, C.byref(_dn()), C.byref(nr),
+                               C.byref(cp), C.byref(out)) == 1                  # n < 1
+    assert lib.snx_plan_create(C.cast(fr, C.c_void_p), 1, C.byref(_dn(window=5)), C.byref(nr),
+                               C.byref(cp), C.byref(out)) == 2                  # window 5
+    bad = (snx_frame * 1)(snx_frame(0x1000, 32, 64, 8, snx_camera(500.0, 500.0, 0.1, 3.0, 3.0),
+                                    0, 0, 0x2000, 64, 0x3000, 0))
+    assert lib.snx_plan_create(C.cast(bad, C.c_void_p), 1, C.byref(_dn()), C.byref(nr),
+                               C.byref(cp), C.byref(out)) == 1                  # stride < width
+    assert lib.snx_plan_run(None, None) == 1

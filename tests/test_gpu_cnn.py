@@ -1,0 +1,183 @@
+"""GPU parity of the learned denoiser against the FP64 oracle (BF16-emulating).
+
+Tolerances:
+  forward   the GPU accumulates in FP32 in MFMA order, the oracle in FP64 rounded
+            to FP32 once; both round every activation to bfloat16 at the same
+            points, so they agree except where an FP32 rounding difference flips
+            a bfloat16 rounding (probability ~ 2^-16 per activation); a flip is
+            one bfloat16 ulp (2^-8 relative) that decays through the remaining
+            layers.  Bound: max |dD~| <= 0.05 px, mean <= 1e-4 px.
+  loss      FP64 head on the same D~ as the oracle: relative 1e-9.
+  gradients the GPU rounds each layer's output gradient to bfloat16 for the MFMA
+            backward-data pass (2^-9 relative per layer); per layer the gradient
+            must have cosine >= 0.995 with the oracle's and relative error <= 0.1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _snx():
+    import paper_2504_15121_amd as snx
+    snx.load()
+    return snx
+
+
+def _params(seed):
+    from oracle import cnn_oracle as cnn
+    rng = np.random.default_rng(seed)
+    p = cnn.init_params(seed)
+    # non-zero last layer so that the network output is not trivially the filter
+    p = [(w + rng.normal(0, 0.05, w.shape) * (k == 5), b + rng.normal(0, 0.02, b.shape))
+         for k, (w, b) in enumerate(p)]
+    flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in p]).astype(np.float32)
+    p32 = [(w.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64))
+           for w, b in p]
+    return flat, p32
+
+
+def _packed(snx, flat):
+    P = torch.from_numpy(flat).to(DEV)
+    packed = torch.empty(snx.snx_cnn_packed_bytes() // 2, dtype=torch.int16, device=DEV)
+    snx.snx_cnn_pack(P, packed)
+    return P, packed
+
+
+@pytest.mark.parametrize("W,H", [(53, 37), (16, 16), (129, 70)])
+def test_forward_matches_oracle(W, H):
+    from oracle import cnn_oracle as cnn
+    snx = _snx()
+    print(f"case cnn forward {W}x{H}", flush=True)
+    flat, p32 = _params(1)
+    P, packed = _packed(snx, flat)
+    sc = scenes.planes_scene(width=W, height=H, f=120.0, seed=W, sigma=0.5, invalid_frac=0.1)
+    ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=DEV)
+    model = snx.cnn_model(P, packed, ws)
+    out = torch.empty((H, W), device=DEV)
+    snx.snx_cnn_denoise(torch.from_numpy(sc.disp).to(DEV), model, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().astype(np.float64)
+    ref = cnn.forward(sc.disp, p32, emulate_bf16=True)
+    assert np.array_equal(np.isnan(g), np.isnan(ref))
+    m = np.isfinite(ref)
+    err = np.abs(g[m] - ref[m])
+    assert err.max() <= 0.05 and err.mean() <= 1e-4, (err.max(), err.mean())
+
+
+def _batch(n, crop, base):
+    crops = [scenes.training_crop(base + i, crop=crop) for i in range(n)]
+    D = np.stack([c.disp for c in crops]).astype(np.float32)
+    N = np.stack([np.moveaxis(c.normal, -1, 0) for c in crops]).astype(np.float32)
+    return crops, D, N
+
+
+def test_loss_and_gradients_match_oracle():
+    from oracle import cnn_oracle as cnn
+    snx = _snx()
+    print("case cnn loss and gradients", flush=True)
+    flat, p32 = _params(2)
+    P, packed = _packed(snx, flat)
+    crop, B, ng = 48, 2, 5
+    crops, D, N = _batch(B, crop, 0)
+    grad = torch.zeros_like(P)
+    mom = torch.zeros_like(P)
+    vel = torch.zeros_like(P)
+    loss = torch.zeros(2, dtype=torch.float64, device=DEV)
+    ws = torch.empty(snx.snx_cnn_workspace_size(crop, crop, B, 1), dtype=torch.uint8, device=DEV)
+    snx.snx_cnn_train_step(torch.from_numpy(D).to(DEV), torch.from_numpy(N).to(DEV),
+                           [c.cam for c in crops], P, packed, grad, mom, vel, 0, 1e-3, loss, ws,
+                           normal_window=ng)
+    torch.cuda.synchronize()
+    gl = loss.cpu().numpy()
+    gg = grad.cpu().numpy().astype(np.float64)
+    parts = []
+    for c in crops:
+        Dt = cnn.forward(c.disp, p32, emulate_bf16=True)
+        L, n, use, dDt = cnn.normal_loss(Dt, c.normal, c.cam, ng)
+        parts.append((L, int(use.sum()), dDt))
+    Ntot = sum(p[1] for p in parts)
+    Lref = sum(p[0] * p[1] for p in parts) / Ntot
+    assert int(gl[1]) == Ntot
+    assert abs(gl[0] - Lref) <= 1e-6 * abs(Lref), (gl[0], Lref)
+    gref = np.zeros_like(gg)
+    for c, (L, u, dDt) in zip(crops, parts):
+        gr = cnn.backward(c.disp, p32, dDt * u / Ntot, emulate_bf16=True)
+        gref += np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in gr])
+    off = 0
+    for k, (w, b) in enumerate(p32):
+        n = w.size + b.size
+        a, r = gg[off:off + n], gref[off:off + n]
+        cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
+        rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+        print(f"layer {k + 1}: cos {cos:.6f} rel {rel:.3e}")
+        assert cos >= 0.995 and rel <= 0.1, (k, cos, rel)
+        off += n
+
+
+def test_training_reduces_loss_and_resumes_bitwise(tmp_path):
+    snx = _snx()
+    from paper_2504_15121_amd import learned
+    print("case cnn training", flush=True)
+    crop, B = 64, 4
+    crops, D, N = _batch(16, crop, 100)
+    pool = (D, N, [c.cam for c in crops])
+    t = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    l0 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False)
+    losses = t.fit(40, pool)
+    l1 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False)
+    assert l1 < l0, (l0, l1)
+    # 5 + 5 steps in one trainer vs 5 steps, checkpoint, fresh trainer, 5 steps:
+    # bit-identical parameters (fixed-order reductions, no atomics in the step)
+    ck = str(tmp_path / "ck.npz")
+    t.save(ck)
+    a = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    a.load(ck)
+    a.fit(5, pool)
+    a.fit(5, pool)
+    b1 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    b1.load(ck)
+    b1.fit(5, pool)
+    mid = str(tmp_path / "mid.npz")
+    b1.save(mid)
+    b2 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    b2.load(mid)
+    b2.fit(5, pool)
+    assert a.step == b2.step
+    np.testing.assert_array_equal(a.params.cpu().numpy(), b2.params.cpu().numpy())
+
+
+def test_learned_pipeline_equals_separate_calls():
+    snx = _snx()
+    from paper_2504_15121_amd import learned
+    print("case learned pipeline", flush=True)
+    flat, _ = _params(3)
+    P, packed = _packed(snx, flat)
+    sc = scenes.planes_quadrics_scene(width=300, height=170, f=300.0, n_planes=8, n_spheres=2,
+                                      seed=9)
+    H, W = sc.disp.shape
+    ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=DEV)
+    model = snx.cnn_model(P, packed, ws)
+    d = torch.from_numpy(sc.disp).to(DEV)
+    dn = torch.empty((H, W), device=DEV)
+    nrm = torch.empty((3, H, W), device=DEV)
+    lab = torch.empty((H, W), dtype=torch.int32, device=DEV)
+    pts = torch.empty((H, W, 8), device=DEV)
+    pws = torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8, device=DEV)
+    snx.snx_pipeline(d, sc.cam, lab, pts, pws, disp_dn=dn, normals=nrm, normal_window=9,
+                     cnn=model)
+    dn2 = torch.empty((H, W), device=DEV)
+    nrm2 = torch.empty((3, H, W), device=DEV)
+    lab2 = torch.empty((H, W), dtype=torch.int32, device=DEV)
+    pts2 = torch.empty((H, W, 8), device=DEV)
+    snx.snx_cnn_denoise(d, model, dn2)
+    snx.snx_affine_normals(dn2, sc.cam, normals=nrm2, window=9)
+    snx.snx_components(d, lab2, pws)
+    snx.snx_point_cloud(dn2, nrm2, lab2, sc.cam, pts2)
+    torch.cuda.synchronize()
+    for a, b in ((dn, dn2), (nrm, nrm2), (lab, lab2), (pts, pts2)):
+        assert torch.equal(a.view(torch.int32), b.view(torch.int32))
