@@ -5,7 +5,9 @@ benchmark).  Plain numpy, no code shared with the GPU path.
 
 Model (a learned stand-in for the hand-tuned filter; the paper notes its method
 is differentiable and convolution-like, Sec. 1 contribution paragraph):
-  mu  = the LSQ plane-fit filter of the disparity (window 3) at valid pixels
+  mu  = the LSQ plane-fit filter of the disparity (window 3) at valid pixels,
+        rounded to float32 (the filter's output type; the network sees the
+        same float32 image a caller of the filter gets)
   x0  = (D - mu) / s at valid pixels, 0 at invalid ones;  x1 = validity (0/1)
   a_1 = relu(conv(W1, [x0, x1]) + b1)            2 -> 32 channels
   a_k = relu(conv(Wk, a_{k-1}) + bk)             32 -> 32, k = 2..5
@@ -107,7 +109,7 @@ def init_params(seed=0):
 def features(D, nf_mu=3, s=S_SCALE):
     D = np.asarray(D, dtype=np.float64)
     valid = np.isfinite(D) & (D > 0)
-    mu = plain.denoise(D, nf_mu)
+    mu = f32(plain.denoise(D, nf_mu))
     x0 = np.where(valid, (np.where(valid, D, 0.0) - np.where(valid, mu, 0.0)) / s, 0.0)
     return mu, valid, np.stack([x0, valid.astype(np.float64)])
 

@@ -115,6 +115,9 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first "
                           "(there is no non-HIP fallback)")
+    # torch brings its own HIP runtime; load it first so that libsnx binds to the
+    # same runtime instance that owns the tensors' memory and streams
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -158,6 +161,16 @@ def _planes(t, n, H, W, name):
             or t.stride(0) != t.shape[1] * t.stride(1)):
         raise ValueError(f"{name}: need a CUDA float32 ({n}, H, S) plane tensor, S >= W")
     return t.stride(1)
+
+
+def _dense(t, dtype, shape, name):
+    """Pointer of a contiguous CUDA tensor of the given dtype and shape (None = any size)."""
+    if (t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or t.dim() != len(shape)
+            or any(s is not None and s != d for s, d in zip(shape, t.shape))):
+        want = "x".join("?" if s is None else str(s) for s in shape)
+        raise ValueError(f"{name}: need a contiguous CUDA {dtype} tensor of shape {want}, "
+                         f"got {t.dtype} {tuple(t.shape)} strides {t.stride()}")
+    return t.data_ptr()
 
 
 def camera(cam) -> snx_camera:
@@ -322,13 +335,26 @@ def snx_cnn_workspace_size(width, height, batch=1, training=False):
     return int(load().snx_cnn_workspace_size(width, height, batch, int(bool(training))))
 
 
+def _params(t, name="params"):
+    import torch
+    return _dense(t, torch.float32, (snx_cnn_param_count(),), name)
+
+
+def _packed(t):
+    if not t.is_cuda or not t.is_contiguous() or t.numel() * t.element_size() < snx_cnn_packed_bytes():
+        raise ValueError(f"packed: need a contiguous CUDA buffer of {snx_cnn_packed_bytes()} bytes")
+    return t.data_ptr()
+
+
 def snx_cnn_pack(params, packed, stream=None):
-    _check(load().snx_cnn_pack(_ptr(params), _ptr(packed), _stream(stream)))
+    _check(load().snx_cnn_pack(_params(params), _packed(packed), _stream(stream)))
 
 
 def cnn_model(params, packed, workspace):
     """snx_cnn_model for the C calls (keep the returned object alive)."""
-    return snx_cnn_model(params.data_ptr(), packed.data_ptr(), workspace.data_ptr(),
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace: need a contiguous CUDA buffer")
+    return snx_cnn_model(_params(params), _packed(packed), workspace.data_ptr(),
                          workspace.numel() * workspace.element_size())
 
 
@@ -345,12 +371,21 @@ def snx_cnn_train_step(disp, normals, cams, params, packed, grad, adam_m, adam_v
                        stream=None):
     """disp (B, H, W) and normals (B, 3, H, W) device float32; cams: list of objects with
     fx, fy, baseline, u0, v0; loss_out device float64[2]."""
+    import torch
     B, H, W = disp.shape
+    if len(cams) != B:
+        raise ValueError("one camera per batch item")
     carr = (snx_camera * B)(*[camera(c) for c in cams])
+    if not workspace.is_cuda or not workspace.is_contiguous():
+        raise ValueError("workspace: need a contiguous CUDA buffer")
     _check(load().snx_cnn_train_step(
-        _ptr(disp), _ptr(normals), C.cast(carr, C.c_void_p), W, H, B, normal_window,
-        _ptr(params), _ptr(packed), _ptr(grad), _ptr(adam_m), _ptr(adam_v), int(step),
-        float(lr), float(beta1), float(beta2), float(eps), _ptr(loss_out), _ptr(workspace),
+        _dense(disp, torch.float32, (B, H, W), "disp"),
+        _dense(normals, torch.float32, (B, 3, H, W), "normals"), C.cast(carr, C.c_void_p),
+        W, H, B, normal_window, _params(params), _packed(packed), _params(grad, "grad"),
+        None if adam_m is None else _params(adam_m, "adam_m"),
+        None if adam_v is None else _params(adam_v, "adam_v"), int(step),
+        float(lr), float(beta1), float(beta2), float(eps),
+        _dense(loss_out, torch.float64, (2,), "loss_out"), workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), _stream(stream)))
 
 

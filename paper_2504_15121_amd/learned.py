@@ -20,6 +20,8 @@ import numpy as np
 from . import _lib
 
 CKPT_VERSION = 1
+MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
+DEFAULT_MODEL = os.path.join(MODEL_DIR, "denoiser_ng9.npz")
 LAYERS = [(2, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
 
 
@@ -38,13 +40,28 @@ def init_params(seed: int = 0) -> np.ndarray:
     return flat
 
 
-def crop_batch(indices, crop=256):
-    """Seeded training crops: disparity (B, H, W), normals (B, 3, H, W), cameras."""
+def _one_crop(args):
+    """Crop i of the training mix: a road-like crop when the running count of road
+    crops, floor((i + 1) * road_frac), steps at i, else a Voronoi-plane crop."""
     from synth import scenes
-    scs = [scenes.training_crop(int(i), crop=crop) for i in indices]
-    D = np.stack([s.disp for s in scs]).astype(np.float32)
-    N = np.stack([np.moveaxis(s.normal, -1, 0) for s in scs]).astype(np.float32)
-    return D, N, [s.cam for s in scs]
+    i, crop = args[0], args[1]
+    road_frac = args[2] if len(args) > 2 else 0.0
+    if np.floor((i + 1) * road_frac) > np.floor(i * road_frac):
+        s = scenes.road_crop(int(i), crop=crop)
+    else:
+        s = scenes.training_crop(int(i), crop=crop)
+    return (np.ascontiguousarray(s.disp, np.float32),
+            np.ascontiguousarray(np.moveaxis(s.normal, -1, 0), np.float32), s.cam)
+
+
+def crop_batch(indices, crop=256, pool=None):
+    """Seeded training crops: disparity (B, H, W), normals (B, 3, H, W), cameras.
+    `pool` (a multiprocessing pool) spreads the generation over processes."""
+    work = [(int(i), crop) for i in indices]
+    res = pool.map(_one_crop, work, chunksize=8) if pool is not None else list(map(_one_crop, work))
+    D = np.ascontiguousarray(np.stack([r[0] for r in res]))
+    N = np.ascontiguousarray(np.stack([r[1] for r in res]))
+    return D, N, [r[2] for r in res]
 
 
 class Trainer:
@@ -72,8 +89,8 @@ class Trainer:
     def train_step(self, D, N, cams, lr=None, apply=True):
         """One Adam step on a batch (numpy or device tensors); returns the loss."""
         torch = self.torch
-        D = torch.as_tensor(D, device=self.dev)
-        N = torch.as_tensor(N, device=self.dev)
+        D = torch.as_tensor(D, device=self.dev).contiguous()
+        N = torch.as_tensor(N, device=self.dev).contiguous()
         step = self.step + 1 if apply else 0
         _lib.snx_cnn_train_step(D, N, cams, self.params, self.packed, self.grad, self.m, self.v,
                                 step, self.lr if lr is None else lr, self.loss, self.ws,
@@ -143,3 +160,72 @@ def load_checkpoint(path):
         raise CheckpointError(f"{path}: CRC mismatch")
     st.update(params=p, m=m, v=v)
     return st
+
+
+# ------------------------------------------------------------------ training CLI
+def train_main(argv=None):
+    """Train the denoiser on seeded crops and write a checkpoint.
+
+    Crops are generated in chunks by a process pool while the GPU trains on the
+    previous chunk; each chunk is used for `--passes` passes in shuffled batches."""
+    import argparse
+    import multiprocessing as mp
+    import time
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2504_15121_amd.learned")
+    ap.add_argument("--crops", type=int, default=20000)
+    ap.add_argument("--chunk", type=int, default=1000)
+    ap.add_argument("--passes", type=int, default=1)
+    ap.add_argument("--crop", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--normal-window", type=int, default=9)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=5e-5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--road-frac", type=float, default=0.5,
+                    help="fraction of road-like crops in the training mix")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--out", default=DEFAULT_MODEL)
+    ap.add_argument("--resume", default=None)
+    a = ap.parse_args(argv)
+
+    _lib.load()
+    t = Trainer(crop=a.crop, batch=a.batch, normal_window=a.normal_window, lr=a.lr, seed=a.seed)
+    if a.resume:
+        t.load(a.resume)
+    rng = np.random.default_rng(a.seed)
+    n_chunks = (a.crops + a.chunk - 1) // a.chunk
+    total_steps = n_chunks * a.passes * (a.chunk // a.batch)
+    k = 0
+    t0 = time.time()
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(a.workers) as pool:
+        nxt = pool.map_async(_one_crop, [(i, a.crop, a.road_frac)
+                                         for i in range(min(a.chunk, a.crops))], chunksize=8)
+        for c in range(n_chunks):
+            res = nxt.get()
+            lo = (c + 1) * a.chunk
+            if lo < a.crops:
+                nxt = pool.map_async(_one_crop, [(i, a.crop, a.road_frac)
+                                                 for i in range(lo, min(lo + a.chunk, a.crops))],
+                                     chunksize=8)
+            D = t.torch.from_numpy(np.ascontiguousarray(np.stack([r[0] for r in res]))).to(t.dev)
+            N = t.torch.from_numpy(np.ascontiguousarray(np.stack([r[1] for r in res]))).to(t.dev)
+            cams = [r[2] for r in res]
+            losses = []
+            for _ in range(a.passes):
+                order = rng.permutation(len(res))
+                for j in range(0, len(res) - a.batch + 1, a.batch):
+                    idx = order[j:j + a.batch]
+                    lr = a.lr_final + 0.5 * (a.lr - a.lr_final) * (1 + np.cos(np.pi * k / total_steps))
+                    ii = t.torch.from_numpy(idx).to(t.dev)
+                    losses.append(t.train_step(D[ii], N[ii], [cams[i] for i in idx], lr=lr))
+                    k += 1
+            print(f"chunk {c + 1}/{n_chunks} step {t.step} loss {np.mean(losses):.5f} "
+                  f"lr {lr:.2e} {time.time() - t0:.1f} s", flush=True)
+            t.save(a.out)
+    return t
+
+
+if __name__ == "__main__":
+    train_main()

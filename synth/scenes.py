@@ -415,6 +415,22 @@ def training_crop(index, crop=256, frame_w=2048, frame_h=1024, f=2260.0,
                    {"kind": "crop", "origin": (ox, oy)})
 
 
+def road_crop(index, crop=256, frame_w=2048, frame_h=1024, f=2260.0, baseline=0.22,
+              sigma_range=(0.1, 1.5), invalid_range=(0.0, 0.15), base_seed=2_000_000):
+    """One road-like training crop (ground plane, facades, boxes, sky) cut from a
+    virtual frame, the crop keeping the frame's principal point."""
+    seed = base_seed + int(index)
+    rng = np.random.default_rng(seed)
+    ox = int(rng.integers(0, frame_w - crop + 1))
+    oy = int(rng.integers(0, frame_h - crop + 1))
+    cam = Camera(f, f, baseline, (frame_w - 1) / 2.0 - ox, (frame_h - 1) / 2.0 - oy)
+    sc = road_scene(width=crop, height=crop, f=f, baseline=baseline,
+                    sigma=float(rng.uniform(*sigma_range)),
+                    invalid_frac=float(rng.uniform(*invalid_range)), seed=seed, cam=cam)
+    sc.meta.update(kind="road_crop", origin=(ox, oy))
+    return sc
+
+
 def workload(name, seed=None):
     """The named single-frame workloads with their evaluation seeds."""
     if name == "planes_640x480":

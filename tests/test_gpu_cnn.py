@@ -4,10 +4,14 @@ Tolerances:
   forward   the GPU accumulates in FP32 in MFMA order, the oracle in FP64 rounded
             to FP32 once; both round every activation to bfloat16 at the same
             points, so they agree except where an FP32 rounding difference flips
-            a bfloat16 rounding (probability ~ 2^-16 per activation); a flip is
-            one bfloat16 ulp (2^-8 relative) that decays through the remaining
-            layers.  Bound: max |dD~| <= 0.05 px, mean <= 1e-4 px.
-  loss      FP64 head on the same D~ as the oracle: relative 1e-9.
+            a bfloat16 rounding (about 2^-16 per activation); a flip is one
+            bfloat16 ulp that spreads through the remaining layers.  Replaying
+            the oracle with FP32 sums in random orders on crops of 48..129 px
+            gave max 0.018 px, mean <= 1.4e-4 px, 99th percentile <= 0.0036 px
+            against the FP64 sums; the bounds are about 3x those:
+            max 0.05, mean 4e-4, p99 0.01.
+  loss      FP64 head on the GPU's own D~ (the same kernels as the denoising
+            call, so bit-identical): relative 1e-9 against the oracle head.
   gradients the GPU rounds each layer's output gradient to bfloat16 for the MFMA
             backward-data pass (2^-9 relative per layer); per layer the gradient
             must have cosine >= 0.995 with the oracle's and relative error <= 0.1.
@@ -66,13 +70,21 @@ def test_forward_matches_oracle(W, H):
     assert np.array_equal(np.isnan(g), np.isnan(ref))
     m = np.isfinite(ref)
     err = np.abs(g[m] - ref[m])
-    assert err.max() <= 0.05 and err.mean() <= 1e-4, (err.max(), err.mean())
+    assert err.max() <= 0.05 and err.mean() <= 4e-4 and np.quantile(err, 0.99) <= 0.01, \
+        (err.max(), err.mean(), np.quantile(err, 0.99))
+
+
+def _cam32(cam):
+    """The camera as the ABI sees it (float32 fields)."""
+    return type(cam)(*[float(np.float32(getattr(cam, k)))
+                       for k in ("fx", "fy", "baseline", "u0", "v0")])
 
 
 def _batch(n, crop, base):
     crops = [scenes.training_crop(base + i, crop=crop) for i in range(n)]
-    D = np.stack([c.disp for c in crops]).astype(np.float32)
-    N = np.stack([np.moveaxis(c.normal, -1, 0) for c in crops]).astype(np.float32)
+    D = np.ascontiguousarray(np.stack([c.disp for c in crops]), np.float32)
+    # np.stack keeps the channel-last memory order of the moved axes: make it dense
+    N = np.ascontiguousarray(np.stack([np.moveaxis(c.normal, -1, 0) for c in crops]), np.float32)
     return crops, D, N
 
 
@@ -92,18 +104,28 @@ def test_loss_and_gradients_match_oracle():
     snx.snx_cnn_train_step(torch.from_numpy(D).to(DEV), torch.from_numpy(N).to(DEV),
                            [c.cam for c in crops], P, packed, grad, mom, vel, 0, 1e-3, loss, ws,
                            normal_window=ng)
+    # a channel-last normals tensor is refused, not misread
+    with pytest.raises(ValueError):
+        snx.snx_cnn_train_step(torch.from_numpy(D).to(DEV),
+                               torch.from_numpy(N).to(DEV).permute(0, 2, 3, 1).contiguous()
+                               .permute(0, 3, 1, 2), [c.cam for c in crops], P, packed, grad,
+                               mom, vel, 0, 1e-3, loss, ws, normal_window=ng)
     torch.cuda.synchronize()
     gl = loss.cpu().numpy()
     gg = grad.cpu().numpy().astype(np.float64)
+    # the GPU's own D~ of each crop, from the denoising call (same kernels)
+    wsi = torch.empty(snx.snx_cnn_workspace_size(crop, crop, 1, 0), dtype=torch.uint8, device=DEV)
     parts = []
-    for c in crops:
-        Dt = cnn.forward(c.disp, p32, emulate_bf16=True)
-        L, n, use, dDt = cnn.normal_loss(Dt, c.normal, c.cam, ng)
+    for b, c in enumerate(crops):
+        o = torch.empty((crop, crop), device=DEV)
+        snx.snx_cnn_denoise(torch.from_numpy(D[b]).to(DEV), snx.cnn_model(P, packed, wsi), o)
+        Dt = o.cpu().numpy().astype(np.float64)
+        L, n, use, dDt = cnn.normal_loss(Dt, c.normal, _cam32(c.cam), ng)
         parts.append((L, int(use.sum()), dDt))
     Ntot = sum(p[1] for p in parts)
     Lref = sum(p[0] * p[1] for p in parts) / Ntot
     assert int(gl[1]) == Ntot
-    assert abs(gl[0] - Lref) <= 1e-6 * abs(Lref), (gl[0], Lref)
+    assert abs(gl[0] - Lref) <= 1e-9 * abs(Lref), (gl[0], Lref)
     gref = np.zeros_like(gg)
     for c, (L, u, dDt) in zip(crops, parts):
         gr = cnn.backward(c.disp, p32, dDt * u / Ntot, emulate_bf16=True)
