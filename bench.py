@@ -14,6 +14,15 @@ a step is still in the 256 MB last-level cache from the previous use.
 Printed: ONE JSON line with value = Mpixel/s of the whole step, a roofline
 object for the dominant kernel (the part-2 kernel, timed with HIP events on the
 stream it runs on) and the FP64 CPU oracle's rate on the host cores.
+
+Beside the headline figure the same line carries the batched forms, each one
+replay of a captured batch plan (snx_plan_run) per step:
+  plain_batched    64 frames of uneven size (planes + quadrics, 640x480 up to
+                   2880x1988, disparities up to 280 px), 3x3 LSQ filter
+  road_batch       256 road-like 2048x1024 frames (f = 2260 px, b = 0.22 m,
+                   sigma = 0.75 px, 10 % invalid): the learned filter batched,
+                   and the plain filter batched, with the mean angular error of
+                   each against the generator's normals on the distinct frames
 """
 import argparse
 import hashlib
@@ -44,7 +53,122 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batch-plan figures")
+    ap.add_argument("--road-frames", type=int, default=256)
+    ap.add_argument("--road-distinct", type=int, default=16,
+                    help="distinct generated road frames (the rest are copies)")
+    ap.add_argument("--uneven-frames", type=int, default=64)
+    ap.add_argument("--batch-steps", type=int, default=5)
     return ap.parse_args()
+
+
+def _pool_map(fn, items):
+    import multiprocessing as mp
+    n = max(1, min(16, os.cpu_count() or 1, len(items)))
+    if n == 1:
+        return [fn(x) for x in items]
+    with mp.get_context("spawn").Pool(n) as pool:
+        return pool.map(fn, items)
+
+
+def _road(seed):
+    from synth import scenes
+    return scenes.road_scene(seed=seed)
+
+
+def angular_error_sum(pts, gt):
+    """(sum of unsigned angles in degrees, count) over pixels where both the
+    record's normal and the ground truth are defined."""
+    import numpy as np
+    n = pts[..., 3:6].astype(np.float64)
+    ok = np.isfinite(n[..., 0]) & np.isfinite(gt[..., 0])
+    cr = np.linalg.norm(np.cross(n[ok], gt[ok]), axis=-1)
+    dt = np.abs((n[ok] * gt[ok]).sum(-1))
+    return float(np.degrees(np.arctan2(cr, dt)).sum()), int(ok.sum())
+
+
+def _time_replays(snx, torch, plan, stream, steps, warmup=2):
+    for _ in range(warmup):
+        plan.run(stream)
+    stream.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        for _ in range(steps):
+            plan.run(stream)
+        b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_batched(args, snx, torch, np, dev, nf, ng):
+    """Batch-plan figures: plain on the uneven batch, learned and plain on the
+    road batch.  Returns the dict that goes into the JSON line."""
+    from synth import scenes
+    from paper_2504_15121_amd import learned
+    out = {}
+    stream = torch.cuda.Stream()
+
+    def frame_bufs(disp, cam):
+        H, W = disp.shape
+        return dict(disp=disp, cam=cam, labels=torch.empty((H, W), dtype=torch.int32, device=dev),
+                    points=torch.empty((H, W, 8), device=dev),
+                    disp_dn=torch.empty((H, W), device=dev),
+                    num_components=torch.zeros(1, dtype=torch.int32, device=dev))
+
+    # ---- plain, uneven batch
+    specs = scenes.uneven_batch_specs(args.uneven_frames, seed=3000)
+    frames = _pool_map(scenes.uneven_frame, specs)
+    bufs = [frame_bufs(torch.from_numpy(f.disp).to(dev), f.cam) for f in frames]
+    px = sum(f.disp.size for f in frames)
+    plan = snx.Plan(bufs, filter_window=nf, normal_window=ng)
+    ms = _time_replays(snx, torch, plan, stream, args.batch_steps)
+    es, ec = 0.0, 0
+    for f, b in zip(frames, bufs):
+        e, c = angular_error_sum(b["points"].cpu().numpy(), f.normal)
+        es, ec = es + e, ec + c
+    out["plain_batched"] = {
+        "workload": f"uneven_{len(frames)}_frames", "frames": len(frames),
+        "megapixels": round(px / 1e6, 2), "ms_per_batch": round(ms, 4),
+        "value": round(px / (ms * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+        "filter": f"lsq{nf}", "normal_window": ng, "mean_angular_error_deg": round(es / ec, 3)}
+    plan.close()
+    del bufs, plan, frames
+    torch.cuda.empty_cache()
+
+    # ---- road batch: learned and plain, both batched
+    distinct = _pool_map(_road, [5000 + i for i in range(args.road_distinct)])
+    n = args.road_frames
+    src = [torch.from_numpy(f.disp).to(dev) for f in distinct]
+    bufs = [frame_bufs(src[i % len(src)].clone(), distinct[i % len(src)].cam) for i in range(n)]
+    px = sum(b["disp"].numel() for b in bufs)
+    ckpt = learned.load_checkpoint(learned.DEFAULT_MODEL)
+    P = torch.from_numpy(ckpt["params"]).to(dev)
+    packed = torch.empty(snx.snx_cnn_packed_bytes() // 2, dtype=torch.int16, device=dev)
+    snx.snx_cnn_pack(P, packed)
+    H, W = distinct[0].disp.shape
+    ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=dev)
+    model = snx.cnn_model(P, packed, ws)
+    road = {"workload": f"road_{n}x2048x1024", "frames": n, "distinct_frames": len(distinct),
+            "megapixels": round(px / 1e6, 2), "normal_window": ng}
+    for tag, kw in (("learned_batched", dict(cnn=model)), ("plain_batched", dict(filter_window=nf))):
+        plan = snx.Plan(bufs, normal_window=ng, **kw)
+        ms = _time_replays(snx, torch, plan, stream, max(2, args.batch_steps // 2))
+        es, ec = 0.0, 0
+        for i, f in enumerate(distinct):
+            e, c = angular_error_sum(bufs[i]["points"].cpu().numpy(), f.normal)
+            es, ec = es + e, ec + c
+        road[tag] = {"ms_per_batch": round(ms, 3), "value": round(px / (ms * 1e-3) / 1e6, 1),
+                     "unit": "Mpixel/s", "mean_angular_error_deg": round(es / ec, 3),
+                     "filter": "cnn" if "cnn" in kw else f"lsq{nf}"}
+        plan.close()
+    road["learned_vs_plain_speed"] = round(road["learned_batched"]["value"] /
+                                           road["plain_batched"]["value"], 3)
+    out["road_batch"] = road
+    del bufs
+    torch.cuda.empty_cache()
+    return out
 
 
 def traffic_from_profiles(kernel_src):
@@ -158,6 +282,8 @@ def main():
                 "kernel": f"k_stencil<0,{ng // 2},{tiles[1]}> (snx_pipeline part 2)",
                 "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(fused_ms, 5)}
 
+    batched = None if args.no_batched else bench_batched(args, snx, torch, np, dev, nf, ng)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import oracle
@@ -190,6 +316,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if batched:
+        out.update(batched)
     print(json.dumps(out), flush=True)
 
 

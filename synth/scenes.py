@@ -297,14 +297,13 @@ def planes_quadrics_scene(width=1920, height=1080, f=1400.0, baseline=0.2,
                     "n_spheres": n_spheres})
 
 
-def uneven_batch(n_frames=64, seed=0, w_range=(640, 2880), h_range=(480, 1988),
-                 f_range=(500.0, 3000.0), b_range=(0.1, 0.3), d_max=280.0,
-                 sigma_range=(0.25, 1.0), invalid_range=(0.05, 0.10),
-                 size_scale=1.0):
-    """Frames of uneven resolution (planes + spheres), disparity in (0, d_max].
-    size_scale < 1 shrinks every frame (for quick tests) keeping the recipe."""
+def uneven_batch_specs(n_frames=64, seed=0, w_range=(640, 2880), h_range=(480, 1988),
+                       f_range=(500.0, 3000.0), b_range=(0.1, 0.3), d_max=280.0,
+                       sigma_range=(0.25, 1.0), invalid_range=(0.05, 0.10),
+                       size_scale=1.0):
+    """Per-frame arguments of uneven_batch (so frames can be generated apart)."""
     rng = np.random.default_rng(seed)
-    frames = []
+    specs = []
     for i in range(n_frames):
         W = int(rng.integers(w_range[0], w_range[1] + 1) * size_scale)
         H = int(rng.integers(h_range[0], h_range[1] + 1) * size_scale)
@@ -315,12 +314,21 @@ def uneven_batch(n_frames=64, seed=0, w_range=(640, 2880), h_range=(480, 1988),
         inv = rng.uniform(*invalid_range)
         z_min = f * b / d_max
         z_max = max(z_min * 40.0, 60.0)
-        frames.append(planes_quadrics_scene(
-            W, H, f, b, n_planes=int(rng.integers(8, 41)),
-            n_spheres=int(rng.integers(2, 11)),
-            z_range=(z_min * 1.2, z_max), sigma=sigma, invalid_frac=inv,
-            seed=int(rng.integers(0, 2**31 - 1))))
-    return frames
+        specs.append(dict(width=W, height=H, f=f, baseline=b,
+                          n_planes=int(rng.integers(8, 41)), n_spheres=int(rng.integers(2, 11)),
+                          z_range=(z_min * 1.2, z_max), sigma=sigma, invalid_frac=inv,
+                          seed=int(rng.integers(0, 2**31 - 1))))
+    return specs
+
+
+def uneven_frame(spec):
+    return planes_quadrics_scene(**spec)
+
+
+def uneven_batch(n_frames=64, seed=0, **kw):
+    """Frames of uneven resolution (planes + spheres), disparity in (0, d_max].
+    size_scale < 1 shrinks every frame (for quick tests) keeping the recipe."""
+    return [uneven_frame(sp) for sp in uneven_batch_specs(n_frames, seed, **kw)]
 
 
 def road_scene(width=2048, height=1024, f=2260.0, baseline=0.22, sigma=0.75,
