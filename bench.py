@@ -171,19 +171,29 @@ def bench_batched(args, snx, torch, np, dev, nf, ng):
     return out
 
 
-def traffic_from_profiles(kernel_src):
-    """HBM bytes per launch of the fused kernel from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+# sources of the part-2 stencil kernel: counters taken on other sources are stale
+STENCIL_SOURCES = ("paper_2504_15121_amd/csrc/stencil.hip", "paper_2504_15121_amd/csrc/lsq.hpp",
+                   "paper_2504_15121_amd/csrc/snx_internal.hpp")
+
+
+def traffic_from_profiles(kernel_name):
+    """HBM bytes per launch of the part-2 kernel from the committed counter
+    summary, or None when it was taken on another kernel instance or on other
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", "k_stencil_planes_quadrics_1920x1080_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     m_sha = re.search(r"source_sha256:\s*([0-9a-f]{64})", txt)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m_sha or not m_b:
+    m_k = re.search(r"^kernel:\s*(.+)$", txt, re.M)
+    if not m_sha or not m_b or not m_k:
         return None
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
-    return float(m_b.group(1)) if sha == m_sha.group(1) else None
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    ok = h.hexdigest() == m_sha.group(1) and kernel_name in m_k.group(1)
+    return float(m_b.group(1)) if ok else None
 
 
 def main():
@@ -274,8 +284,7 @@ def main():
     mean_err = float(np.degrees(np.arctan2(cr, dt)).mean())
 
     achieved = FUSED_BYTES_PER_PX * px / (fused_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(os.path.join(ROOT, "paper_2504_15121_amd", "csrc",
-                                                 "stencil.hip"))
+    traffic = traffic_from_profiles(f"k_stencil<0, {ng // 2}, {tiles[1]}>")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
