@@ -46,7 +46,7 @@ typedef enum snx_status {
     SNX_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. window too large)   */
     SNX_ERR_WORKSPACE = 3,    /* workspace missing or too small                   */
     SNX_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed       */
-    SNX_ERR_MODEL = 5         /* reserved for learned-filter models               */
+    SNX_ERR_MODEL = 5         /* learned filter requested without a complete model */
 } snx_status;
 
 /* Rectified pin-hole pair (Sec. 2, projections Pi_1 and Pi_2): focal lengths in
@@ -268,7 +268,7 @@ snx_status snx_tune_set(int32_t width, int32_t height, int32_t filter_window,
 /* ===========================================================================
  * Learned residual denoiser (stands in for the LSQ filter; the paper notes the
  * method is differentiable and convolution-like, Sec. 1).
- *   mu = LSQ filter (window 3); x = [(D - mu)/s, valid] with s = 1 px;
+ *   mu = LSQ filter (window 3) as float32; x = [(D - mu)/s, valid], s = 1 px;
  *   six 3x3 convolutions 2->32, 4 x 32->32 (ReLU), 32->1, zero padding;
  *   D~ = mu + s*y at valid pixels, NaN elsewhere.
  * Weights and activations are bfloat16 with float32 accumulation (MFMA).
