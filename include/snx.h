@@ -299,16 +299,23 @@ snx_status snx_cnn_denoise(const float *disp, int64_t stride, int32_t width, int
  *   disp      device, batch x height x width (contiguous)
  *   normals   device, batch x 3 x height x width ground-truth unit normals
  *             (NaN where there is none)
+ *   clean     device, batch x height x width noise-free disparity (NaN where
+ *             there is none), or NULL for no fidelity term
  *   cams      host, `batch` cameras (principal point relative to each crop);
  *             batch <= 64
- * Loss = mean over pixels with a defined normal (slope window normal_window)
- * and a ground-truth normal of 1 - n . n_gt; its gradient flows through the
- * normal, the slope, the residual and the network.  grad receives the
- * parameter gradient.  step >= 1 then applies Adam (moments adam_m, adam_v,
- * bias correction for this step number) to params and repacks `packed`;
- * step == 0 only computes loss and grad.  loss_out: device double[2]
- * (loss, number of pixels).  Deterministic: fixed-order reductions only. */
-snx_status snx_cnn_train_step(const float *disp, const float *normals, const snx_camera *cams,
+ * Loss = L_n + fidelity * L_f with
+ *   L_n = mean over pixels with a defined normal (slope window normal_window)
+ *         and a ground-truth normal of 1 - n . n_gt,
+ *   L_f = mean over pixels with a valid D~ and a finite clean value of
+ *         (D~ - clean)^2  (px^2; keeps D~ an unbiased disparity for z and x, y);
+ * the gradient flows through the normal, the slope, the residual and the
+ * network.  grad receives the parameter gradient.  step >= 1 then applies Adam
+ * (moments adam_m, adam_v, bias correction for this step number) to params and
+ * repacks `packed`; step == 0 only computes loss and grad.  loss_out: device
+ * double[4] = (loss, number of normal pixels, L_n, L_f).  Deterministic:
+ * fixed-order reductions only. */
+snx_status snx_cnn_train_step(const float *disp, const float *normals, const float *clean,
+                              float fidelity, const snx_camera *cams,
                               int32_t width, int32_t height, int32_t batch,
                               int32_t normal_window, float *params, void *packed, float *grad,
                               float *adam_m, float *adam_v, int32_t step, float lr,

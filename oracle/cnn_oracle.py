@@ -22,10 +22,12 @@ FP64 (used for finite-difference pins).
 
 Training loss (normals supervise the denoiser through the method's own
 gradient and normal steps, Sec. 3.1-3.3):
-  L = sum over pixels c with a defined normal and a ground-truth normal g_c of
-      (1 - n_c . g_c) / N
+  L_n = sum over pixels c with a defined normal and a ground-truth normal g_c of
+        (1 - n_c . g_c) / N
 with n_c the unit normal from the anchored masked LSQ slope of D~ (window n_g),
-N the number of such pixels.
+N the number of such pixels; optionally plus w * L_f with the fidelity term
+  L_f = mean over pixels with a valid D~ and a finite clean disparity of
+        (D~ - clean)^2.
 """
 from __future__ import annotations
 
@@ -228,7 +230,23 @@ def backward(D, params, dL_dDt, emulate_bf16=True, nf_mu=3, s=S_SCALE):
     return grads
 
 
-def loss_and_grads(D, params, n_gt, cam, ng=9, emulate_bf16=True, nf_mu=3, s=S_SCALE):
+def fidelity_loss(Dt, clean):
+    """Mean squared difference between D~ and the clean disparity over pixels
+    where D~ is valid and the clean value finite; returns (L_f, count, dL_f/dD~)."""
+    Dt = np.asarray(Dt, dtype=np.float64)
+    clean = np.asarray(clean, dtype=np.float64)
+    m = np.isfinite(Dt) & (Dt > 0) & np.isfinite(clean)
+    n = int(m.sum())
+    r = np.where(m, np.where(m, Dt, 0.0) - np.where(m, clean, 0.0), 0.0)
+    nn = max(n, 1)
+    return float((r * r).sum() / nn), n, 2.0 * r / nn
+
+
+def loss_and_grads(D, params, n_gt, cam, ng=9, emulate_bf16=True, nf_mu=3, s=S_SCALE,
+                   clean=None, w=0.0):
     Dt = forward(D, params, emulate_bf16, nf_mu, s)
     L, n, use, dDt = normal_loss(Dt, n_gt, cam, ng)
+    if clean is not None:
+        Lf, _, dF = fidelity_loss(Dt, clean)
+        L, dDt = L + w * Lf, dDt + w * dF
     return L, backward(D, params, dDt, emulate_bf16, nf_mu, s)

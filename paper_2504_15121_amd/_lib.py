@@ -92,8 +92,9 @@ SIGNATURES = {
     "snx_cnn_workspace_size": (_SZ, [_I32, _I32, _I32, _I32]),
     "snx_cnn_pack": (_I32, [_P, _P, _P]),
     "snx_cnn_denoise": (_I32, [_P, _I64, _I32, _I32, _P, _P, _I64, _P]),
-    "snx_cnn_train_step": (_I32, [_P, _P, _P, _I32, _I32, _I32, _I32, _P, _P, _P, _P, _P, _I32,
-                                  C.c_float, C.c_float, C.c_float, C.c_float, _P, _P, _SZ, _P]),
+    "snx_cnn_train_step": (_I32, [_P, _P, _P, C.c_float, _P, _I32, _I32, _I32, _I32, _P, _P,
+                                  _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float,
+                                  _P, _P, _SZ, _P]),
     "snx_plan_create": (_I32, [_P, _I32, C.POINTER(snx_denoise_params),
                                C.POINTER(snx_normal_params), C.POINTER(snx_component_params),
                                C.POINTER(C.c_void_p)]),
@@ -368,9 +369,9 @@ def snx_cnn_denoise(disp, model, out, stream=None):
 
 def snx_cnn_train_step(disp, normals, cams, params, packed, grad, adam_m, adam_v, step, lr,
                        loss_out, workspace, normal_window=9, beta1=0.9, beta2=0.999, eps=1e-8,
-                       stream=None):
+                       stream=None, clean=None, fidelity=0.0):
     """disp (B, H, W) and normals (B, 3, H, W) device float32; cams: list of objects with
-    fx, fy, baseline, u0, v0; loss_out device float64[2]."""
+    fx, fy, baseline, u0, v0; loss_out device float64[4]; clean (B, H, W) float32 or None."""
     import torch
     B, H, W = disp.shape
     if len(cams) != B:
@@ -380,12 +381,14 @@ def snx_cnn_train_step(disp, normals, cams, params, packed, grad, adam_m, adam_v
         raise ValueError("workspace: need a contiguous CUDA buffer")
     _check(load().snx_cnn_train_step(
         _dense(disp, torch.float32, (B, H, W), "disp"),
-        _dense(normals, torch.float32, (B, 3, H, W), "normals"), C.cast(carr, C.c_void_p),
+        _dense(normals, torch.float32, (B, 3, H, W), "normals"),
+        None if clean is None else _dense(clean, torch.float32, (B, H, W), "clean"),
+        float(fidelity), C.cast(carr, C.c_void_p),
         W, H, B, normal_window, _params(params), _packed(packed), _params(grad, "grad"),
         None if adam_m is None else _params(adam_m, "adam_m"),
         None if adam_v is None else _params(adam_v, "adam_v"), int(step),
         float(lr), float(beta1), float(beta2), float(eps),
-        _dense(loss_out, torch.float64, (2,), "loss_out"), workspace.data_ptr(),
+        _dense(loss_out, torch.float64, (4,), "loss_out"), workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), _stream(stream)))
 
 

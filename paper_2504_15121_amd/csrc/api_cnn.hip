@@ -52,9 +52,9 @@ CnnWs carve(char *base, int W, int H, int B, bool training)
         w.grad_y = (float *)take(px * 4);
         w.partial = (float *)take((size_t)snx::cnn_partial_blocks(W, H, B) * snx::kLayerParams[1] * 4);
         const size_t hb = (size_t)snx::cnn_head_blocks(W, H, B);
-        w.part_loss = (double *)take(hb * 8);
-        w.part_used = (int *)take(hb * 4);
-        w.inv_n = (float *)take(4);
+        w.part_loss = (double *)take(hb * 16);
+        w.part_used = (int *)take(hb * 8);
+        w.inv_n = (float *)take(8);
     }
     w.bytes = off;
     return w;
@@ -140,7 +140,8 @@ snx_status snx_cnn_denoise(const float *disp, int64_t stride, int32_t width, int
     return e == hipSuccess ? SNX_OK : api_hip_fail(e, "snx_cnn_denoise");
 }
 
-snx_status snx_cnn_train_step(const float *disp, const float *normals, const snx_camera *cams,
+snx_status snx_cnn_train_step(const float *disp, const float *normals, const float *clean,
+                              float fidelity, const snx_camera *cams,
                               int32_t width, int32_t height, int32_t batch,
                               int32_t normal_window, float *params, void *packed, float *grad,
                               float *adam_m, float *adam_v, int32_t step, float lr,
@@ -153,6 +154,8 @@ snx_status snx_cnn_train_step(const float *disp, const float *normals, const snx
         return api_fail(SNX_ERR_ARG, "NULL argument");
     if (step < 0 || (step > 0 && (!adam_m || !adam_v)))
         return api_fail(SNX_ERR_ARG, "step < 0 or Adam moments missing");
+    if (!(isfinite(fidelity) && fidelity >= 0))
+        return api_fail(SNX_ERR_ARG, "fidelity weight must be finite and >= 0");
     if (normal_window < 3 || normal_window % 2 == 0 || normal_window > 63)
         return api_fail(SNX_ERR_ARG, "normal_window must be odd, 3..63");
     for (int b = 0; b < batch; ++b)
@@ -196,6 +199,8 @@ snx_status snx_cnn_train_step(const float *disp, const float *normals, const snx
     h.need_g = (normal_window * normal_window + 1) / 2;
     h.Dt = w.dt;
     h.n_gt = normals;
+    h.clean = clean;
+    h.fid_w = clean ? fidelity : 0.0f;
     for (int b = 0; b < batch; ++b) h.cams[b] = {cams[b].fx, cams[b].fy, cams[b].u0, cams[b].v0};
     h.coefA = w.coefA;
     h.coefB = w.coefB;

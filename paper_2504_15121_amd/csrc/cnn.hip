@@ -389,7 +389,8 @@ __global__ void k_wgrad_reduce(const float *partial, int64_t nblk, int nt, float
 //   Gu = G . (f_x, 0, -(u-u0)),  Gv = G . (0, f_y, -(v-v0)),
 //   A = (gamma Gu - beta Gv)/det,  B = (-beta Gu + alpha Gv)/det,
 //   own = G_z - (A Sx + B Sy);
-// partial sums of the loss and of the number of used pixels per workgroup.
+// partial sums of the loss and of the number of used pixels per workgroup, and
+// of the fidelity term (D~ - clean)^2 and its pixel count.
 // ----------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_head(HeadArgs a)
@@ -400,12 +401,20 @@ k_head(HeadArgs a)
     const int W = a.W, H = a.H, r = a.rg;
     const int64_t plane = (int64_t)W * H;
     const float *D = a.Dt + (int64_t)b * plane;
-    double loss = 0.0;
-    int used = 0;
+    double loss = 0.0, fid = 0.0;
+    int used = 0, fused_px = 0;
     if (gx < W && gy < H) {
         const int64_t o = (int64_t)b * plane + (int64_t)gy * W + gx;
         float A = 0.0f, B = 0.0f, own = 0.0f;
         const float Dc = D[(int64_t)gy * W + gx];
+        if (a.clean && valid_disp(Dc)) {
+            const float c = a.clean[o];
+            if (c - c == 0.0f) {
+                const double r = (double)Dc - (double)c;
+                fid = r * r;
+                fused_px = 1;
+            }
+        }
         if (valid_disp(Dc)) {
             int N = 0, Sx = 0, Sy = 0, al = 0, be = 0, ga = 0;
             double P1 = 0.0, P2 = 0.0;
@@ -453,35 +462,50 @@ k_head(HeadArgs a)
         a.coefOwn[o] = own;
     }
     // workgroup partials (fixed order: wave ballots then lane 0 of wave 0)
-    __shared__ double sl[256];
-    __shared__ int su[256];
+    __shared__ double sl[256], sf[256];
+    __shared__ int su[256], sc[256];
     sl[threadIdx.x] = loss;
     su[threadIdx.x] = used;
+    sf[threadIdx.x] = fid;
+    sc[threadIdx.x] = fused_px;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double L = 0.0;
-        int U = 0;
-        for (int i = 0; i < 256; ++i) { L += sl[i]; U += su[i]; }
+        double L = 0.0, F = 0.0;
+        int U = 0, C = 0;
+        for (int i = 0; i < 256; ++i) { L += sl[i]; U += su[i]; F += sf[i]; C += sc[i]; }
         const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        a.part_loss[blk] = L;
-        a.part_used[blk] = U;
+        a.part_loss[2 * blk] = L;
+        a.part_loss[2 * blk + 1] = F;
+        a.part_used[2 * blk] = U;
+        a.part_used[2 * blk + 1] = C;
     }
 }
 
-__global__ void k_head_total(const double *pl, const int *pu, int64_t n, double *loss_out,
-                             float *inv_n)
+__global__ void k_head_total(const double *pl, const int *pu, int64_t n, float fid_w,
+                             double *loss_out, float *inv_n)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double L = 0.0;
-    long long U = 0;
-    for (int64_t k = 0; k < n; ++k) { L += pl[k]; U += pu[k]; }
+    double L = 0.0, F = 0.0;
+    long long U = 0, C = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        L += pl[2 * k];
+        F += pl[2 * k + 1];
+        U += pu[2 * k];
+        C += pu[2 * k + 1];
+    }
     const double N = U > 0 ? (double)U : 1.0;
-    loss_out[0] = L / N;
+    const double NF = C > 0 ? (double)C : 1.0;
+    const double Ln = L / N, Lf = F / NF;
+    loss_out[0] = Ln + (double)fid_w * Lf;
     loss_out[1] = (double)U;
+    loss_out[2] = Ln;
+    loss_out[3] = Lf;
     inv_n[0] = (float)(1.0 / N);
+    inv_n[1] = (float)(2.0 * (double)fid_w / NF);
 }
 
-// dL/dy at pixel j = s / N * valid_j * (own_j - sum_d (A_{j+d} d_x + B_{j+d} d_y))
+// dL/dy at pixel j = s * valid_j * [(own_j - sum_d (A_{j+d} d_x + B_{j+d} d_y)) / N
+//                                  + 2 w (D~_j - clean_j) / N_f]
 __global__ void __launch_bounds__(256)
 k_head_bwd(HeadArgs a)
 {
@@ -493,7 +517,8 @@ k_head_bwd(HeadArgs a)
     const int64_t plane = (int64_t)W * H;
     const int64_t base = (int64_t)b * plane;
     float g = 0.0f;
-    if (valid_disp(a.Dt[base + (int64_t)gy * W + gx])) {
+    const float Dc = a.Dt[base + (int64_t)gy * W + gx];
+    if (valid_disp(Dc)) {
         float s = a.coefOwn[base + (int64_t)gy * W + gx];
         for (int dy = -r; dy <= r; ++dy) {
             const int yy = gy + dy;
@@ -505,7 +530,12 @@ k_head_bwd(HeadArgs a)
                 s -= a.coefA[o] * dx + a.coefB[o] * dy;
             }
         }
-        g = s * a.inv_n[0] * a.s;
+        float f = 0.0f;
+        if (a.clean) {
+            const float c = a.clean[base + (int64_t)gy * W + gx];
+            if (c - c == 0.0f) f = (Dc - c) * a.inv_n[1];
+        }
+        g = (s * a.inv_n[0] + f) * a.s;
     }
     a.grad_y[base + (int64_t)gy * W + gx] = g;
 }
@@ -617,7 +647,7 @@ hipError_t cnn_head(const HeadArgs &h, double *loss_out, hipStream_t s)
     if (e != hipSuccess) return e;
     const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
     hipLaunchKernelGGL(k_head_total, dim3(1), dim3(64), 0, s, h.part_loss, h.part_used, nblk,
-                       loss_out, h.inv_n);
+                       h.fid_w, loss_out, h.inv_n);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_head_bwd, grid, dim3(256), 0, s, h);

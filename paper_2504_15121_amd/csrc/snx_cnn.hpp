@@ -59,10 +59,12 @@ struct HeadArgs {
     const float *Dt;           // B x H x W denoised disparity
     const float *n_gt;         // B x 3 x H x W ground-truth normals (NaN = none)
     CnnCam cams[kCnnMaxBatch]; // passed by value with the launch
+    const float *clean;        // B x H x W noise-free disparity (NaN = none), or null
+    float fid_w;               // weight of the fidelity term
     float *coefA, *coefB, *coefOwn;   // B x H x W
-    double *part_loss;
-    int *part_used;
-    float *inv_n;              // device scalar 1/N
+    double *part_loss;         // per workgroup: sum of 1 - n.g, sum of (D~ - clean)^2
+    int *part_used;            // per workgroup: normal pixels, fidelity pixels
+    float *inv_n;              // device: 1/N (normal term), 2 w / N_f (fidelity term)
     float *grad_y;             // B x H x W dL/dy
     float s;
 };

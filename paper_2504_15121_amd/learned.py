@@ -51,27 +51,30 @@ def _one_crop(args):
     else:
         s = scenes.training_crop(int(i), crop=crop)
     return (np.ascontiguousarray(s.disp, np.float32),
-            np.ascontiguousarray(np.moveaxis(s.normal, -1, 0), np.float32), s.cam)
+            np.ascontiguousarray(np.moveaxis(s.normal, -1, 0), np.float32), s.cam,
+            np.ascontiguousarray(s.clean, np.float32))
 
 
-def crop_batch(indices, crop=256, pool=None):
-    """Seeded training crops: disparity (B, H, W), normals (B, 3, H, W), cameras.
-    `pool` (a multiprocessing pool) spreads the generation over processes."""
-    work = [(int(i), crop) for i in indices]
+def crop_batch(indices, crop=256, pool=None, road_frac=0.0):
+    """Seeded training crops: disparity (B, H, W), normals (B, 3, H, W), cameras,
+    clean disparity (B, H, W).  `pool` (a multiprocessing pool) spreads the
+    generation over processes."""
+    work = [(int(i), crop, road_frac) for i in indices]
     res = pool.map(_one_crop, work, chunksize=8) if pool is not None else list(map(_one_crop, work))
     D = np.ascontiguousarray(np.stack([r[0] for r in res]))
     N = np.ascontiguousarray(np.stack([r[1] for r in res]))
-    return D, N, [r[2] for r in res]
+    Cl = np.ascontiguousarray(np.stack([r[3] for r in res]))
+    return D, N, [r[2] for r in res], Cl
 
 
 class Trainer:
     def __init__(self, device="cuda:0", crop=256, batch=8, normal_window=9, lr=1e-3,
-                 seed=0, params=None):
+                 seed=0, params=None, fidelity=0.0):
         import torch
         self.torch = torch
         self.dev = torch.device(device)
         self.crop, self.batch, self.normal_window = crop, batch, normal_window
-        self.lr, self.seed = lr, seed
+        self.lr, self.seed, self.fidelity = lr, seed, fidelity
         p = init_params(seed) if params is None else np.asarray(params, np.float32)
         self.params = torch.from_numpy(p.copy()).to(self.dev)
         n = self.params.numel()
@@ -80,38 +83,46 @@ class Trainer:
         self.v = torch.zeros(n, dtype=torch.float32, device=self.dev)
         self.packed = torch.empty(_lib.snx_cnn_packed_bytes() // 2, dtype=torch.int16,
                                   device=self.dev)
-        self.loss = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        self.loss = torch.zeros(4, dtype=torch.float64, device=self.dev)
         self.ws = torch.empty(_lib.snx_cnn_workspace_size(crop, crop, batch, True),
                               dtype=torch.uint8, device=self.dev)
         self.step = 0
         _lib.snx_cnn_pack(self.params, self.packed)
 
-    def train_step(self, D, N, cams, lr=None, apply=True):
+    def train_step(self, D, N, cams, lr=None, apply=True, clean=None):
         """One Adam step on a batch (numpy or device tensors); returns the loss."""
         torch = self.torch
         D = torch.as_tensor(D, device=self.dev).contiguous()
         N = torch.as_tensor(N, device=self.dev).contiguous()
+        if clean is not None and self.fidelity > 0:
+            clean = torch.as_tensor(clean, device=self.dev).contiguous()
+        else:
+            clean = None
         step = self.step + 1 if apply else 0
         _lib.snx_cnn_train_step(D, N, cams, self.params, self.packed, self.grad, self.m, self.v,
                                 step, self.lr if lr is None else lr, self.loss, self.ws,
-                                normal_window=self.normal_window)
+                                normal_window=self.normal_window, clean=clean,
+                                fidelity=self.fidelity)
         if apply:
             self.step += 1
         return float(self.loss[0].item())
 
     def fit(self, n_steps, pool, log_every=0, lr_final=None):
-        """Train on crops cycled from `pool` (D, N, cams); cosine learning-rate decay
-        to lr_final (default lr / 10)."""
-        D, N, cams = pool
+        """Train on crops cycled from `pool` (D, N, cams[, clean]); cosine
+        learning-rate decay to lr_final (default lr / 10)."""
+        D, N, cams = pool[:3]
+        Cl = pool[3] if len(pool) > 3 else None
         lr_final = self.lr / 10 if lr_final is None else lr_final
         losses = []
         n = D.shape[0]
         Dd = self.torch.as_tensor(D, device=self.dev)
         Nd = self.torch.as_tensor(N, device=self.dev)
+        Cd = None if Cl is None else self.torch.as_tensor(Cl, device=self.dev)
         for k in range(n_steps):
             idx = [(k * self.batch + j) % n for j in range(self.batch)]
             lr = lr_final + 0.5 * (self.lr - lr_final) * (1 + np.cos(np.pi * k / max(1, n_steps)))
-            loss = self.train_step(Dd[idx], Nd[idx], [cams[i] for i in idx], lr=lr)
+            loss = self.train_step(Dd[idx], Nd[idx], [cams[i] for i in idx], lr=lr,
+                                   clean=None if Cd is None else Cd[idx])
             losses.append(loss)
             if log_every and (k + 1) % log_every == 0:
                 print(f"step {self.step} loss {loss:.5f} lr {lr:.2e}", flush=True)
@@ -127,7 +138,7 @@ class Trainer:
         v = self.v.cpu().numpy()
         crc = zlib.crc32(p.tobytes() + m.tobytes() + v.tobytes())
         return dict(version=CKPT_VERSION, params=p, m=m, v=v, step=self.step, seed=self.seed,
-                    crc=crc)
+                    normal_window=self.normal_window, fidelity=self.fidelity, crc=crc)
 
     def save(self, path):
         tmp = path + ".tmp.npz"
@@ -184,13 +195,16 @@ def train_main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--road-frac", type=float, default=0.5,
                     help="fraction of road-like crops in the training mix")
+    ap.add_argument("--fidelity", type=float, default=0.1,
+                    help="weight of the (D~ - clean)^2 term (px^-2)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--out", default=DEFAULT_MODEL)
     ap.add_argument("--resume", default=None)
     a = ap.parse_args(argv)
 
     _lib.load()
-    t = Trainer(crop=a.crop, batch=a.batch, normal_window=a.normal_window, lr=a.lr, seed=a.seed)
+    t = Trainer(crop=a.crop, batch=a.batch, normal_window=a.normal_window, lr=a.lr, seed=a.seed,
+                fidelity=a.fidelity)
     if a.resume:
         t.load(a.resume)
     rng = np.random.default_rng(a.seed)
@@ -212,6 +226,7 @@ def train_main(argv=None):
             D = t.torch.from_numpy(np.ascontiguousarray(np.stack([r[0] for r in res]))).to(t.dev)
             N = t.torch.from_numpy(np.ascontiguousarray(np.stack([r[1] for r in res]))).to(t.dev)
             cams = [r[2] for r in res]
+            Cl = t.torch.from_numpy(np.ascontiguousarray(np.stack([r[3] for r in res]))).to(t.dev)
             losses = []
             for _ in range(a.passes):
                 order = rng.permutation(len(res))
@@ -219,10 +234,13 @@ def train_main(argv=None):
                     idx = order[j:j + a.batch]
                     lr = a.lr_final + 0.5 * (a.lr - a.lr_final) * (1 + np.cos(np.pi * k / total_steps))
                     ii = t.torch.from_numpy(idx).to(t.dev)
-                    losses.append(t.train_step(D[ii], N[ii], [cams[i] for i in idx], lr=lr))
+                    losses.append(t.train_step(D[ii], N[ii], [cams[i] for i in idx], lr=lr,
+                                               clean=Cl[ii]))
                     k += 1
+            ln, lf = t.loss[2].item(), t.loss[3].item()
             print(f"chunk {c + 1}/{n_chunks} step {t.step} loss {np.mean(losses):.5f} "
-                  f"lr {lr:.2e} {time.time() - t0:.1f} s", flush=True)
+                  f"(last: normal {ln:.4f}, fidelity {lf:.4f} px^2) lr {lr:.2e} "
+                  f"{time.time() - t0:.1f} s", flush=True)
             t.save(a.out)
     return t
 

@@ -168,13 +168,15 @@ def test_cnn_sizes_and_validation(lib):
     assert lib.snx_cnn_denoise(FAKE, 64, 64, 8, None, FAKE, 64, None) == 5
     from paper_2504_15121_amd._lib import snx_camera
     cams = (snx_camera * 1)(snx_camera(500.0, 500.0, 0.1, 10.0, 10.0))
-    args = [FAKE, FAKE, C.cast(cams, C.c_void_p), 64, 64, 1, 9, FAKE, FAKE, FAKE, FAKE, FAKE, 1,
-            C.c_float(1e-3), C.c_float(0.9), C.c_float(0.999), C.c_float(1e-8), FAKE, FAKE, 10,
-            None]
+    args = [FAKE, FAKE, None, C.c_float(0.0), C.cast(cams, C.c_void_p), 64, 64, 1, 9, FAKE,
+            FAKE, FAKE, FAKE, FAKE, 1, C.c_float(1e-3), C.c_float(0.9), C.c_float(0.999),
+            C.c_float(1e-8), FAKE, FAKE, 10, None]
     assert lib.snx_cnn_train_step(*args) == 3          # workspace too small
-    bad = list(args); bad[6] = 4                         # even window
+    bad = list(args); bad[8] = 4                         # even window
     assert lib.snx_cnn_train_step(*bad) == 1
-    bad = list(args); bad[10] = None                     # Adam moments missing
+    bad = list(args); bad[12] = None                     # Adam moments missing
+    assert lib.snx_cnn_train_step(*bad) == 1
+    bad = list(args); bad[3] = C.c_float(-1.0)           # negative fidelity weight
     assert lib.snx_cnn_train_step(*bad) == 1
 
 

@@ -88,22 +88,29 @@ def _batch(n, crop, base):
     return crops, D, N
 
 
-def test_loss_and_gradients_match_oracle():
+def _clean(crops):
+    return np.ascontiguousarray(np.stack([c.clean for c in crops]), np.float32)
+
+
+@pytest.mark.parametrize("fid", [0.0, 0.1])
+def test_loss_and_gradients_match_oracle(fid):
     from oracle import cnn_oracle as cnn
     snx = _snx()
-    print("case cnn loss and gradients", flush=True)
+    print(f"case cnn loss and gradients, fidelity weight {fid}", flush=True)
     flat, p32 = _params(2)
     P, packed = _packed(snx, flat)
     crop, B, ng = 48, 2, 5
     crops, D, N = _batch(B, crop, 0)
+    Cl = _clean(crops)
     grad = torch.zeros_like(P)
     mom = torch.zeros_like(P)
     vel = torch.zeros_like(P)
-    loss = torch.zeros(2, dtype=torch.float64, device=DEV)
+    loss = torch.zeros(4, dtype=torch.float64, device=DEV)
     ws = torch.empty(snx.snx_cnn_workspace_size(crop, crop, B, 1), dtype=torch.uint8, device=DEV)
     snx.snx_cnn_train_step(torch.from_numpy(D).to(DEV), torch.from_numpy(N).to(DEV),
                            [c.cam for c in crops], P, packed, grad, mom, vel, 0, 1e-3, loss, ws,
-                           normal_window=ng)
+                           normal_window=ng, clean=torch.from_numpy(Cl).to(DEV) if fid else None,
+                           fidelity=fid)
     # a channel-last normals tensor is refused, not misread
     with pytest.raises(ValueError):
         snx.snx_cnn_train_step(torch.from_numpy(D).to(DEV),
@@ -115,21 +122,30 @@ def test_loss_and_gradients_match_oracle():
     gg = grad.cpu().numpy().astype(np.float64)
     # the GPU's own D~ of each crop, from the denoising call (same kernels)
     wsi = torch.empty(snx.snx_cnn_workspace_size(crop, crop, 1, 0), dtype=torch.uint8, device=DEV)
-    parts = []
+    Dts, parts = [], []
     for b, c in enumerate(crops):
         o = torch.empty((crop, crop), device=DEV)
         snx.snx_cnn_denoise(torch.from_numpy(D[b]).to(DEV), snx.cnn_model(P, packed, wsi), o)
         Dt = o.cpu().numpy().astype(np.float64)
+        Dts.append(Dt)
         L, n, use, dDt = cnn.normal_loss(Dt, c.normal, _cam32(c.cam), ng)
         parts.append((L, int(use.sum()), dDt))
     Ntot = sum(p[1] for p in parts)
-    Lref = sum(p[0] * p[1] for p in parts) / Ntot
+    Ln = sum(p[0] * p[1] for p in parts) / Ntot
+    # the fidelity term over the whole batch (one mean over all its pixels)
+    Lf, nf, dF = cnn.fidelity_loss(np.stack(Dts), Cl.astype(np.float64))
+    w32 = float(np.float32(fid))            # the ABI takes the weight as float32
+    Lref = Ln + w32 * Lf
     assert int(gl[1]) == Ntot
+    assert abs(gl[2] - Ln) <= 1e-9 * abs(Ln), (gl[2], Ln)
+    if fid:
+        assert abs(gl[3] - Lf) <= 1e-9 * abs(Lf), (gl[3], Lf)
     assert abs(gl[0] - Lref) <= 1e-9 * abs(Lref), (gl[0], Lref)
     gref = np.zeros_like(gg)
-    for c, (L, u, dDt) in zip(crops, parts):
-        gr = cnn.backward(c.disp, p32, dDt * u / Ntot, emulate_bf16=True)
-        gref += np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in gr])
+    for b, (c, (L, u, dDt)) in enumerate(zip(crops, parts)):
+        up = dDt * u / Ntot + (fid * dF[b] if fid else 0.0)
+        gr = cnn.backward(c.disp, p32, up, emulate_bf16=True)
+        gref += np.concatenate([np.concatenate([w.ravel(), b_.ravel()]) for w, b_ in gr])
     off = 0
     for k, (w, b) in enumerate(p32):
         n = w.size + b.size
@@ -147,26 +163,27 @@ def test_training_reduces_loss_and_resumes_bitwise(tmp_path):
     print("case cnn training", flush=True)
     crop, B = 64, 4
     crops, D, N = _batch(16, crop, 100)
-    pool = (D, N, [c.cam for c in crops])
-    t = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
-    l0 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False)
+    Cl = _clean(crops)
+    pool = (D, N, [c.cam for c in crops], Cl)
+    t = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5, fidelity=0.1)
+    l0 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False, clean=Cl[:B])
     losses = t.fit(40, pool)
-    l1 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False)
+    l1 = t.train_step(D[:B], N[:B], pool[2][:B], apply=False, clean=Cl[:B])
     assert l1 < l0, (l0, l1)
     # 5 + 5 steps in one trainer vs 5 steps, checkpoint, fresh trainer, 5 steps:
     # bit-identical parameters (fixed-order reductions, no atomics in the step)
     ck = str(tmp_path / "ck.npz")
     t.save(ck)
-    a = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    a = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5, fidelity=0.1)
     a.load(ck)
     a.fit(5, pool)
     a.fit(5, pool)
-    b1 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    b1 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5, fidelity=0.1)
     b1.load(ck)
     b1.fit(5, pool)
     mid = str(tmp_path / "mid.npz")
     b1.save(mid)
-    b2 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5)
+    b2 = learned.Trainer(crop=crop, batch=B, normal_window=9, lr=2e-3, seed=5, fidelity=0.1)
     b2.load(mid)
     b2.fit(5, pool)
     assert a.step == b2.step

@@ -112,3 +112,25 @@ def test_network_backward_finite_differences():
         bm[k][1][j] -= 1e-6
         fd = (objective(bp) - objective(bm)) / 2e-6
         assert abs(fd - grads[k][1][j]) <= 1e-5 * max(1.0, abs(fd))
+
+
+def test_fidelity_term_closed_form_and_gradient():
+    """A constant offset c on the valid pixels gives L_f = c^2 exactly; the
+    gradient matches central differences; invalid D~ and missing clean values
+    are excluded."""
+    rng = np.random.default_rng(6)
+    clean = rng.uniform(5, 50, (9, 11))
+    clean[0, 0] = np.nan
+    Dt = clean + 0.75
+    Dt[3, 4] = np.nan
+    Dt[5, 5] = -1.0
+    L, n, g = cnn.fidelity_loss(Dt, clean)
+    assert n == 9 * 11 - 3
+    assert abs(L - 0.75 ** 2) < 1e-12
+    Dt = clean + rng.normal(0, 0.5, clean.shape)
+    L, n, g = cnn.fidelity_loss(Dt, clean)
+    for j in rng.choice(np.flatnonzero(np.isfinite(clean)), 10, replace=False):
+        Dp = Dt.copy(); Dp.flat[j] += 1e-6
+        Dm = Dt.copy(); Dm.flat[j] -= 1e-6
+        fd = (cnn.fidelity_loss(Dp, clean)[0] - cnn.fidelity_loss(Dm, clean)[0]) / 2e-6
+        assert abs(fd - g.flat[j]) < 1e-8
