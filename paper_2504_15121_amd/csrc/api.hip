@@ -294,10 +294,14 @@ static snx_status fused_impl(const float *disp, int64_t stride, int32_t width, i
     return e == hipSuccess ? SNX_OK : hip_fail(e, who);
 }
 
+// Arguments of the fused and pipeline calls; with `one_kernel` also that the
+// filter and the gradient fit one tile (the fused call), else that each fits
+// its own pass (the pipeline filters in a pass of its own when rf > 1).
 static snx_status check_fused(const float *disp, int64_t stride, int32_t width, int32_t height,
                               const snx_camera *cam, const snx_denoise_params *denoise,
                               const snx_normal_params *normal, float *disp_dn, float *affine,
-                              float *normals, int64_t out_stride, snx_point *points)
+                              float *normals, int64_t out_stride, snx_point *points,
+                              bool one_kernel = true)
 {
     snx_status st;
     if ((st = check_denoise(denoise)) || (st = check_normal(normal))) return st;
@@ -308,8 +312,16 @@ static snx_status check_fused(const float *disp, int64_t stride, int32_t width, 
     if ((disp_dn || affine || normals) && out_stride < width)
         return fail(SNX_ERR_ARG, "out_stride < width");
     snx::StencilArgs a;
-    return fill_stencil(a, disp, stride, width, height, denoise->window / 2, normal->window / 2,
-                        need_f(denoise), need_g(normal), cam);
+    const bool cnn = denoise->mode == SNX_FILTER_CNN;
+    const int rf = cnn ? 0 : denoise->window / 2;
+    if (one_kernel)
+        return fill_stencil(a, disp, stride, width, height, rf, normal->window / 2,
+                            need_f(denoise), need_g(normal), cam);
+    if (rf > 1 && (st = fill_stencil(a, disp, stride, width, height, rf, 0, need_f(denoise), 0,
+                                     nullptr)))
+        return st;
+    return fill_stencil(a, disp, stride, width, height, 0, normal->window / 2, 0,
+                        need_g(normal), cam);
 }
 
 snx_status snx_oriented_point_cloud(const float *disp, int64_t stride, int32_t width,
@@ -359,7 +371,7 @@ snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, i
     snx_status st;
     if ((st = check_comp(comp))) return st;
     if ((st = check_fused(disp, stride, width, height, cam, denoise, normal, disp_dn, affine,
-                          normals, out_stride, points)))
+                          normals, out_stride, points, false)))
         return st;
     hipStream_t s = (hipStream_t)stream;
     if (width == 0 || height == 0) {

@@ -123,6 +123,7 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
     int th = snx::tuned_tile_height(0, rg, maxW, maxH);
     if (!snx::batch_has_instance(rg, th)) th = 16;
     if (!snx::batch_has_instance(rg, th)) th = 8;
+    if (!snx::batch_has_instance(rg, th)) th = 4;
     if (!snx::batch_has_instance(rg, th))
         return api_fail(SNX_ERR_UNSUPPORTED, "no batched kernel for this gradient window");
 

@@ -279,6 +279,9 @@ constexpr Inst kInst[] = {
     {0, 4, 8, kfn<0, 4, 8>()},   {0, 4, 16, kfn<0, 4, 16>()}, {0, 4, 32, kfn<0, 4, 32>()},
     {0, 7, 8, kfn<0, 7, 8>()},   {0, 7, 16, kfn<0, 7, 16>()}, {0, 7, 32, kfn<0, 7, 32>()},
     {0, 10, 8, kfn<0, 10, 8>()}, {0, 10, 16, kfn<0, 10, 16>()},
+    {0, 15, 8, kfn<0, 15, 8>()}, {0, 15, 16, kfn<0, 15, 16>()},
+    {0, 22, 4, kfn<0, 22, 4>()}, {0, 22, 8, kfn<0, 22, 8>()},
+    {0, 30, 4, kfn<0, 30, 4>()}, {0, 30, 8, kfn<0, 30, 8>()},
     // fused 3x3 filter + gradient (snx_oriented_point_cloud)
     {1, 1, 16, kfn<1, 1, 16>()}, {1, 2, 16, kfn<1, 2, 16>()}, {1, 3, 16, kfn<1, 3, 16>()},
     {1, 4, 8, kfn<1, 4, 8>()},   {1, 4, 16, kfn<1, 4, 16>()}, {1, 4, 32, kfn<1, 4, 32>()},
@@ -301,7 +304,8 @@ constexpr BatchInst kBatchInst[] = {
     {1, 16, &k_back_batch<1, 16>}, {2, 16, &k_back_batch<2, 16>}, {3, 16, &k_back_batch<3, 16>},
     {4, 8, &k_back_batch<4, 8>},   {4, 16, &k_back_batch<4, 16>}, {4, 32, &k_back_batch<4, 32>},
     {7, 8, &k_back_batch<7, 8>},   {7, 16, &k_back_batch<7, 16>}, {10, 8, &k_back_batch<10, 8>},
-    {10, 16, &k_back_batch<10, 16>},
+    {10, 16, &k_back_batch<10, 16>}, {15, 8, &k_back_batch<15, 8>}, {22, 4, &k_back_batch<22, 4>},
+    {30, 4, &k_back_batch<30, 4>},
 };
 
 bool batch_has_instance(int rg, int th)
@@ -330,17 +334,19 @@ bool stencil_has_instance(int rf, int rg, int th)
     return false;
 }
 
-// Default tile height: 16 when it fits 64 KB of LDS (several workgroups per CU),
-// else the tallest that fits 64 KB, else the tallest that fits the 160 KB of one
-// gfx950 CU.
+// Default tile height: the first of 16, 8, 4, 32 that has an unrolled instance
+// and fits 64 KB of LDS (several workgroups per CU), else one with an instance
+// that fits the 160 KB of one gfx950 CU, else the tallest that fits for the
+// generic (runtime-window) kernel.
 int stencil_pick_tile_height(int rf, int rg)
 {
-    for (int th : {16, 8, 4}) {
-        if (stencil_lds_bytes(rf, rg, th) <= 64 * 1024) return th;
-    }
-    for (int th : {16, 8, 4, 2, 1}) {
-        if (stencil_lds_bytes(rf, rg, th) <= 160 * 1024) return th;
-    }
+    for (size_t cap : {(size_t)64 * 1024, (size_t)160 * 1024})
+        for (int th : {16, 8, 4, 32})
+            if (stencil_has_instance(rf, rg, th) && stencil_lds_bytes(rf, rg, th) <= cap)
+                return th;
+    for (size_t cap : {(size_t)64 * 1024, (size_t)160 * 1024})
+        for (int th : {16, 8, 4, 2, 1})
+            if (stencil_lds_bytes(rf, rg, th) <= cap) return th;
     return 0;
 }
 

@@ -70,7 +70,7 @@ def _check(snx, frames, filter_window, normal_window, cnn=None):
 SPECS = [(300, 170), (64, 32), (1, 1), (517, 333), (65, 33), (1280, 720)]
 
 
-@pytest.mark.parametrize("filter_window,normal_window", [(3, 9), (1, 5), (3, 21)])
+@pytest.mark.parametrize("filter_window,normal_window", [(3, 9), (1, 5), (3, 21), (3, 45), (1, 61)])
 def test_plan_direct_matches_pipeline(filter_window, normal_window):
     snx = _snx()
     print(f"case plan direct f{filter_window} g{normal_window}", flush=True)

@@ -214,6 +214,31 @@ def test_sizes_and_edges(oracle, H, W, nf, ng, nanfrac, pad):
     _same(g, run_oriented(D, cam, nf, ng, pad=pad))
 
 
+@pytest.mark.parametrize("nf,ng", [(3, 45), (5, 45), (1, 61), (5, 61), (9, 23)])
+def test_large_windows(oracle, nf, ng):
+    """Gradient windows up to 61: the pipeline filters in a pass of its own when
+    filter and gradient do not fit one tile; the one-kernel call refuses such
+    windows with SNX_ERR_UNSUPPORTED instead."""
+    snx = _snx()
+    H, W = 150, 131
+    print(f"case large windows nf={nf} ng={ng}", flush=True)
+    rng = np.random.default_rng(ng * 10 + nf)
+    cam = scenes.Camera.centred(W, H, 300.0, 0.125)
+    v, u = np.mgrid[0:H, 0:W]
+    D = (40.0 + 0.15 * u - 0.12 * v + rng.normal(0, 0.4, (H, W))).astype(np.float32)
+    D[rng.random((H, W)) < 0.07] = np.nan
+    g = run_separate(D, cam, nf, ng)
+    check_parity(oracle, D, cam, nf, ng, g)
+    _same(g, run_fused(D, cam, nf, ng))
+    _same(g, run_parts(D, cam, nf, ng))
+    try:
+        o = run_oriented(D, cam, nf, ng)
+    except snx.SnxError as e:
+        assert e.status == 2, e
+    else:
+        _same(g, o)
+
+
 def test_planes_quadrics_1920x1080_fused(oracle):
     sc = scenes.workload("planes_quadrics_1920x1080")
     cam = _cam32(sc.cam)
