@@ -277,9 +277,9 @@ snx_status snx_tune_set(int32_t width, int32_t height, int32_t filter_window,
  * derived from the parameters by snx_cnn_pack (and by snx_cnn_train_step).
  * ========================================================================= */
 typedef struct snx_cnn_model {
-    const float *params;    /* device, snx_cnn_param_count() floats */
-    const void *packed;     /* device, filled by snx_cnn_pack */
-    void *workspace;        /* device, >= snx_cnn_workspace_size(w, h, 1, 0) */
+    const float *params;    /* device, snx_cnn_param_count() floats, 16-byte aligned */
+    const void *packed;     /* device, filled by snx_cnn_pack, 16-byte aligned */
+    void *workspace;        /* device, >= snx_cnn_workspace_size(w, h, 1, 0), 16-byte aligned */
     size_t workspace_bytes;
 } snx_cnn_model;
 

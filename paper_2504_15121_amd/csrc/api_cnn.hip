@@ -1,5 +1,6 @@
 // C ABI of the learned denoiser: validation, workspace carving and launches.
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include "snx_cnn.hpp"
@@ -37,13 +38,9 @@ CnnWs carve(char *base, int W, int H, int B, bool training)
         return p;
     };
     w.mu = (float *)take(px * 4);
-    const int nact = training ? 5 : 2;
-    for (int i = 0; i < nact; ++i) w.acts[i] = (uint16_t *)take(px * 64);
-    if (!training) {
-        w.acts[2] = w.acts[0];
-        w.acts[3] = w.acts[1];
-        w.acts[4] = w.acts[0];
-    } else {
+    // inference keeps every activation in LDS (fused kernel): only mu is needed
+    if (training) {
+        for (int i = 0; i < 5; ++i) w.acts[i] = (uint16_t *)take(px * 64);
         for (int i = 0; i < 2; ++i) w.gbuf[i] = (uint16_t *)take(px * 64);
         w.dt = (float *)take(px * 4);
         w.coefA = (float *)take(px * 4);
@@ -59,6 +56,8 @@ CnnWs carve(char *base, int W, int H, int B, bool training)
     w.bytes = off;
     return w;
 }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 bool dims_ok(int32_t w, int32_t h, int32_t b)
 {
@@ -103,6 +102,8 @@ size_t snx_cnn_workspace_size(int32_t width, int32_t height, int32_t batch, int3
 snx_status snx_cnn_pack(const float *params, void *packed, void *stream)
 {
     if (!params || !packed) return api_fail(SNX_ERR_ARG, "params or packed is NULL");
+    if (!aligned16(params) || !aligned16(packed))
+        return api_fail(SNX_ERR_ARG, "params and packed must be 16-byte aligned");
     hipError_t e = snx::cnn_pack(params, (uint16_t *)packed, (hipStream_t)stream);
     return e == hipSuccess ? SNX_OK : api_hip_fail(e, "snx_cnn_pack");
 }
@@ -117,26 +118,27 @@ snx_status snx_cnn_denoise(const float *disp, int64_t stride, int32_t width, int
         return api_fail(SNX_ERR_ARG, "disp/out NULL or stride < width");
     if (!model || !model->params || !model->packed || !model->workspace)
         return api_fail(SNX_ERR_MODEL, "model, params, packed or workspace is NULL");
+    if (!aligned16(model->params) || !aligned16(model->packed) || !aligned16(model->workspace))
+        return api_fail(SNX_ERR_ARG, "model buffers must be 16-byte aligned");
     const CnnWs w0 = carve(nullptr, width, height, 1, false);
     if (model->workspace_bytes < w0.bytes) return api_fail(SNX_ERR_WORKSPACE, "cnn workspace too small");
     const CnnWs w = carve((char *)model->workspace, width, height, 1, false);
     hipStream_t s = (hipStream_t)stream;
     snx_status st = run_mu(disp, stride, width, height, 1, 0, w.mu, s);
     if (st) return st;
-    snx::CnnForwardArgs f;
+    snx::CnnFusedArgs f;
     memset(&f, 0, sizeof f);
     f.W = width;
     f.H = height;
-    f.B = 1;
     f.D = disp;
     f.ldD = stride;
     f.mu = w.mu;
     f.params = model->params;
     f.packed = (const uint16_t *)model->packed;
-    for (int i = 0; i < 5; ++i) f.acts[i] = w.acts[i];
     f.out = out;
     f.ld_out = out_stride;
-    hipError_t e = snx::cnn_forward(f, s);
+    f.s = snx::kCnnScale;
+    hipError_t e = snx::cnn_forward_fused(f, s);
     return e == hipSuccess ? SNX_OK : api_hip_fail(e, "snx_cnn_denoise");
 }
 
@@ -152,6 +154,8 @@ snx_status snx_cnn_train_step(const float *disp, const float *normals, const flo
     if (batch > snx::kCnnMaxBatch) return api_fail(SNX_ERR_UNSUPPORTED, "batch > 64");
     if (!disp || !normals || !cams || !params || !packed || !grad || !loss_out)
         return api_fail(SNX_ERR_ARG, "NULL argument");
+    if (!aligned16(params) || !aligned16(packed) || !aligned16(workspace))
+        return api_fail(SNX_ERR_ARG, "params, packed and workspace must be 16-byte aligned");
     if (step < 0 || (step > 0 && (!adam_m || !adam_v)))
         return api_fail(SNX_ERR_ARG, "step < 0 or Adam moments missing");
     if (!(isfinite(fidelity) && fidelity >= 0))

@@ -82,7 +82,21 @@ struct CnnForwardArgs {
     int64_t ld_out, crop_stride_out;
 };
 
+// Inference with all six layers fused per 16 x 16 tile (one frame).
+struct CnnFusedArgs {
+    int W, H;
+    const float *D;            // raw disparity, row stride ldD
+    int64_t ldD;
+    const float *mu;           // LSQ filter, H x W contiguous
+    const float *params;
+    const uint16_t *packed;
+    float *out;                // D~, row stride ld_out
+    int64_t ld_out;
+    float s;
+};
+
 hipError_t cnn_pack(const float *params, uint16_t *packed, hipStream_t s);
+hipError_t cnn_forward_fused(const CnnFusedArgs &f, hipStream_t s);
 hipError_t cnn_forward(const CnnForwardArgs &f, hipStream_t s);
 hipError_t cnn_head(const HeadArgs &h, double *loss_out, hipStream_t s);
 hipError_t cnn_backward(const CnnForwardArgs &f, const float *grad_y, float *partial,

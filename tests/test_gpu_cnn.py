@@ -52,19 +52,27 @@ def _packed(snx, flat):
     return P, packed
 
 
-@pytest.mark.parametrize("W,H", [(53, 37), (16, 16), (129, 70)])
-def test_forward_matches_oracle(W, H):
+@pytest.mark.parametrize("W,H,pad", [(53, 37, 0), (16, 16, 0), (129, 70, 3), (1, 1, 0),
+                                     (5, 3, 2), (17, 33, 0), (200, 9, 0)])
+def test_forward_matches_oracle(W, H, pad):
     from oracle import cnn_oracle as cnn
     snx = _snx()
-    print(f"case cnn forward {W}x{H}", flush=True)
+    print(f"case cnn forward {W}x{H} pad {pad}", flush=True)
     flat, p32 = _params(1)
     P, packed = _packed(snx, flat)
-    sc = scenes.planes_scene(width=W, height=H, f=120.0, seed=W, sigma=0.5, invalid_frac=0.1)
+    sc = scenes.planes_scene(width=max(W, 2), height=max(H, 2), f=120.0, seed=W, sigma=0.5,
+                             invalid_frac=0.1)
+    sc.disp = np.ascontiguousarray(sc.disp[:H, :W])
     ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=DEV)
     model = snx.cnn_model(P, packed, ws)
-    out = torch.empty((H, W), device=DEV)
-    snx.snx_cnn_denoise(torch.from_numpy(sc.disp).to(DEV), model, out)
+    din = torch.full((H, W + pad), 7.0, device=DEV)
+    din[:, :W] = torch.from_numpy(sc.disp).to(DEV)
+    out_full = torch.full((H, W + pad), -3.0, device=DEV)
+    out = out_full[:, :W]
+    snx.snx_cnn_denoise(din[:, :W], model, out)
     torch.cuda.synchronize()
+    if pad:
+        assert torch.all(out_full[:, W:] == -3.0)       # nothing written past the row
     g = out.cpu().numpy().astype(np.float64)
     ref = cnn.forward(sc.disp, p32, emulate_bf16=True)
     assert np.array_equal(np.isnan(g), np.isnan(ref))
