@@ -346,8 +346,9 @@ typedef struct snx_frame {
 
 typedef struct snx_plan snx_plan;
 
-/* Validates every frame, picks the tile height (autotuned if snx_autotune ran
- * for the largest frame's size class), allocates the device frame table and
+/* Validates every frame, picks the tile height (the autotuned one for the
+ * largest frame's size class, tuning it now if snx_autotune has not run for
+ * that class), allocates the device frame table and
  * any per-frame scratch (a label forest when label_stride != width, the
  * filtered plane when disp_dn is NULL).  The filter window must be 1 or 3, or
  * mode SNX_FILTER_CNN with a model whose workspace fits the largest frame.

@@ -28,6 +28,7 @@ struct snx_plan {
     std::vector<snx::BatchFrame> host;
     snx::BatchFrame *d_frames = nullptr;
     int *d_front_off = nullptr, *d_back_off = nullptr, *d_counters = nullptr;
+    int *d_front_frame = nullptr, *d_back_frame = nullptr, *d_merge_frame = nullptr;
     int64_t *d_seam_off = nullptr;
     int64_t seam_total = 0;
     int grid_front = 1, grid_back = 1;
@@ -53,6 +54,9 @@ void release(snx_plan *p)
     (void)hipFree(p->d_back_off);
     (void)hipFree(p->d_seam_off);
     (void)hipFree(p->d_counters);
+    (void)hipFree(p->d_front_frame);
+    (void)hipFree(p->d_back_frame);
+    (void)hipFree(p->d_merge_frame);
     delete p;
 }
 
@@ -68,13 +72,13 @@ hipError_t enqueue(snx_plan *p, hipStream_t s)
                 return hipErrorLaunchFailure;
         }
     }
-    if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->n, p->rf, p->d_counters,
-                                     p->grid_front, s)) != hipSuccess)
+    if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->d_front_frame, p->n, p->rf,
+                                     p->d_counters, p->grid_front, s)) != hipSuccess)
         return e;
-    if ((e = snx::launch_batch_merge(p->d_frames, p->d_seam_off, p->n, p->seam_total, s)) !=
-        hipSuccess)
+    if ((e = snx::launch_batch_merge(p->d_frames, p->d_seam_off, p->d_merge_frame, p->n,
+                                     p->seam_total, s)) != hipSuccess)
         return e;
-    return snx::launch_batch_back(p->d_frames, p->d_back_off, p->n, p->rg, p->th,
+    return snx::launch_batch_back(p->d_frames, p->d_back_off, p->d_back_frame, p->n, p->rg, p->th,
                                   p->d_counters + 1, p->grid_back, s);
 }
 
@@ -120,7 +124,14 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
             return api_fail(SNX_ERR_WORKSPACE, "CNN workspace too small for a frame");
         if ((int64_t)f.width * f.height > (int64_t)maxW * maxH) { maxW = f.width; maxH = f.height; }
     }
+    const int need_g = np->min_support > 0 ? np->min_support : (np->window * np->window + 1) / 2;
     int th = snx::tuned_tile_height(0, rg, maxW, maxH);
+    if (th == 0) {
+        // not tuned for this size class yet: tune the gradient pass on the
+        // largest frame's size (a set-up cost of a few milliseconds)
+        hipError_t te = snx::autotune_stencil(0, rg, 3, need_g, maxW, maxH, nullptr, &th);
+        if (te != hipSuccess) return api_hip_fail(te, "snx_plan_create autotune");
+    }
     if (!snx::batch_has_instance(rg, th)) th = 16;
     if (!snx::batch_has_instance(rg, th)) th = 8;
     if (!snx::batch_has_instance(rg, th)) th = 4;
@@ -176,7 +187,7 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         b.back.H = f.height;
         b.back.rf = 0;
         b.back.rg = rg;
-        b.back.need_g = np->min_support > 0 ? np->min_support : (np->window * np->window + 1) / 2;
+        b.back.need_g = need_g;
         b.back.fx = f.cam.fx;
         b.back.fy = f.cam.fy;
         b.back.b = f.cam.baseline;
@@ -192,6 +203,28 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         boff[i + 1] = boff[i] + snx::back_tiles(f.width, f.height, th);
         soff[i + 1] = soff[i] + snx::merge_pairs(f.width, f.height);
     }
+    // item -> frame tables (front tiles, back tiles) and the frame of each
+    // merge block's first seam pair
+    std::vector<int> front_frame(foff[n]), back_frame(boff[n]);
+    for (int i = 0; i < n; ++i) {
+        for (int t = foff[i]; t < foff[i + 1]; ++t) front_frame[t] = i;
+        for (int t = boff[i]; t < boff[i + 1]; ++t) back_frame[t] = i;
+    }
+    const int64_t merge_blocks = (soff[n] + 255) / 256;
+    std::vector<int> merge_frame((size_t)(merge_blocks > 0 ? merge_blocks : 1), 0);
+    for (int i = 0, f = 0; i < merge_blocks; ++i) {
+        while (soff[f + 1] <= (int64_t)i * 256) ++f;
+        merge_frame[i] = f;
+    }
+    auto upload = [&](int **dst, const std::vector<int> &v) {
+        if (e != hipSuccess) return;
+        e = hipMalloc(dst, sizeof(int) * (v.empty() ? 1 : v.size()));
+        if (e == hipSuccess && !v.empty())
+            e = hipMemcpy(*dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice);
+    };
+    upload(&p->d_front_frame, front_frame);
+    upload(&p->d_back_frame, back_frame);
+    upload(&p->d_merge_frame, merge_frame);
     if (e == hipSuccess) e = hipMalloc(&p->d_frames, sizeof(snx::BatchFrame) * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_front_off, sizeof(int) * (n + 1));
     if (e == hipSuccess) e = hipMalloc(&p->d_back_off, sizeof(int) * (n + 1));

@@ -137,27 +137,28 @@ k_front(FrontArgs a)
 // fetch items with an atomic counter until the list is exhausted.
 template <int RF>
 __global__ void __launch_bounds__(kFrontWaves * 64)
-k_front_batch(const BatchFrame *frames, const int *tile_off, int n, int *counter)
+k_front_batch(const BatchFrame *frames, const int *tile_off, const int *tile_frame, int n,
+              int *counter)
 {
     __shared__ FrontSmem<RF> sm;
     __shared__ int item;
     const int total = tile_off[n];
-    while (true) {
-        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = item;
-        __syncthreads();
-        if (it >= total) break;
-        int lo = 0, hi = n - 1;            // frame f with tile_off[f] <= it < tile_off[f+1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_off[mid] <= it) lo = mid; else hi = mid - 1;
-        }
-        const FrontArgs a = frames[lo].front;
-        const int local = it - tile_off[lo];
+    if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+    __syncthreads();
+    int it = item;
+    while (it < total) {
+        // the next item is claimed now, so the atomic's latency overlaps this tile
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(counter, 1);
+        const int f = tile_frame[it];
+        const FrontArgs a = frames[f].front;
+        const int local = it - tile_off[f];
         const int tx = (a.W + kCW - 1) / kCW;
         front_tile<RF>(a, local % tx, local / tx, sm);
         __syncthreads();
+        if (threadIdx.x == 0) item = nxt;
+        __syncthreads();
+        it = item;
     }
 }
 
@@ -217,19 +218,18 @@ k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs
 }
 
 // Seam pairs of every frame of a batch, one thread each.
+// Pair i of the batch; the frame of a block's first pair comes from a table and
+// the frames of later pairs in the block by stepping forward.
 __global__ void __launch_bounds__(256)
-k_merge_batch(const BatchFrame *frames, const int64_t *seam_off, int n)
+k_merge_batch(const BatchFrame *frames, const int64_t *seam_off, const int *block_frame, int n)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= seam_off[n]) return;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (seam_off[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    const FrontArgs &a = frames[lo].front;
+    int f = block_frame[blockIdx.x];
+    while (seam_off[f + 1] <= i) ++f;
+    const FrontArgs &a = frames[f].front;
     const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
-    merge_pair(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.forest, tx - 1, ty - 1, i - seam_off[lo]);
+    merge_pair(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.forest, tx - 1, ty - 1, i - seam_off[f]);
 }
 
 // Work counters and per-frame component counts start at zero on every run.
@@ -243,6 +243,9 @@ __global__ void k_batch_reset(int *counters, int n_counters, const BatchFrame *f
 __global__ void __launch_bounds__(256)
 k_ccl_flatten(CclArgs a)
 {
+    __shared__ int s_roots;   // roots of this block, one global atomic per block
+    if (threadIdx.x == 0) s_roots = 0;
+    __syncthreads();
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
     const bool in = gx < a.W && gy < a.H;
@@ -262,7 +265,9 @@ k_ccl_flatten(CclArgs a)
     }
     if (a.count) {
         const unsigned long long b = __ballot(root);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd(a.count, (int)__popcll(b));
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd(&s_roots, (int)__popcll(b));
+        __syncthreads();
+        if (threadIdx.x == 0 && s_roots) atomicAdd(a.count, s_roots);
     }
 }
 
@@ -301,26 +306,26 @@ int64_t merge_pairs(int W, int H)
     return (int64_t)(tx - 1) * H + (int64_t)(ty - 1) * W;
 }
 
-hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, int n, int rf,
-                              int *counter, int grid, hipStream_t s)
+hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
+                              int n, int rf, int *counter, int grid, hipStream_t s)
 {
     if (rf == 0)
         hipLaunchKernelGGL(k_front_batch<0>, dim3(grid), dim3(kFrontWaves * 64), 0, s, frames,
-                           tile_off, n, counter);
+                           tile_off, tile_frame, n, counter);
     else if (rf == 1)
         hipLaunchKernelGGL(k_front_batch<1>, dim3(grid), dim3(kFrontWaves * 64), 0, s, frames,
-                           tile_off, n, counter);
+                           tile_off, tile_frame, n, counter);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off, int n,
-                              int64_t total, hipStream_t s)
+hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off,
+                              const int *block_frame, int n, int64_t total, hipStream_t s)
 {
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       frames, seam_off, n);
+                       frames, seam_off, block_frame, n);
     return hipGetLastError();
 }
 

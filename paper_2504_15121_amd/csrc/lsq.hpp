@@ -66,10 +66,77 @@ __device__ __forceinline__ RowMom row_moments(const float *p, int r_rt)
     return m;
 }
 
+// Row moments of KRUN consecutive centres p[r], p[r+1], ... (windows
+// p[i .. i+2r]) written to ab[i], s[i] in the column-pass format: the first by
+// direct sums, the others by sliding the window one pixel (remove the left
+// tap, add the right one, re-centre).  Every sum is of integers or of float32
+// values in FP64, exact for windows up to 63 and disparities spanning fewer
+// than 2^29 between smallest and largest, so the results equal the direct sums.
+template <int RC, int KRUN>
+__device__ __forceinline__ void row_moments_run(const float *p, int r_rt, int2 *ab, double2 *s)
+{
+    const int r = RC >= 0 ? RC : r_rt;
+    int n = 0, sx = 0, sxx = 0;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k <= 2 * r; ++k) {
+        const float v = p[k];
+        const int dx = k - r;
+        const int m = v > 0.0f ? 1 : 0;
+        n += m;
+        sx += m * dx;
+        sxx += m * dx * dx;
+        const double dv = (double)v;
+        s0 += dv;
+        s1 += (double)dx * dv;
+    }
+    ab[0] = make_int2(n + (sx + kColOff) * 65536, sxx);
+    s[0] = make_double2(s0, s1);
+#pragma unroll
+    for (int i = 1; i < KRUN; ++i) {
+        const float vo = p[i - 1], vn = p[i + 2 * r];
+        const int mo = vo > 0.0f ? 1 : 0, mn = vn > 0.0f ? 1 : 0;
+        const int t = sx + r * mo + (r + 1) * mn;              // sum of j m_j, j = -r+1 .. r+1
+        const int u = sxx - r * r * mo + (r + 1) * (r + 1) * mn;
+        n += mn - mo;
+        sx = t - n;
+        sxx = u - 2 * t + n;
+        const double dvo = (double)vo, dvn = (double)vn;
+        s0 = (s0 - dvo) + dvn;
+        s1 = ((s1 + (double)r * dvo) + (double)(r + 1) * dvn) - s0;
+        ab[i] = make_int2(n + (sx + kColOff) * 65536, sxx);
+        s[i] = make_double2(s0, s1);
+    }
+}
+
 struct ColMom {
     int N, Sx, Sy, Sxx, Sxy, Syy;
     double R0, Rx, Ry;
 };
+
+// Moves the column window of `m` (rows top .. top+2r of the row-moment arrays,
+// stride apart) down by one row: removes row `top`, adds row top + 2r + 1 and
+// re-centres.  Exact like row_moments_run.
+__device__ __forceinline__ ColMom col_slide(const ColMom &m, const int2 *ab_top, const double2 *s_top,
+                                            int stride, int r)
+{
+    const int2 wo = ab_top[0], wn = ab_top[(2 * r + 1) * stride];
+    const double2 dO = s_top[0], dN = s_top[(2 * r + 1) * stride];
+    const int c0o = wo.x & 0xffff, c1o = (wo.x >> 16) - kColOff, c2o = wo.y;
+    const int c0n = wn.x & 0xffff, c1n = (wn.x >> 16) - kColOff, c2n = wn.y;
+    ColMom o;
+    o.N = m.N - c0o + c0n;
+    o.Sx = m.Sx - c1o + c1n;
+    o.Sxx = m.Sxx - c2o + c2n;
+    const int t0 = m.Sy + r * c0o + (r + 1) * c0n;           // sum of j c0_j over the new rows
+    o.Sy = t0 - o.N;
+    o.Syy = (m.Syy - r * r * c0o + (r + 1) * (r + 1) * c0n) - 2 * t0 + o.N;
+    o.Sxy = (m.Sxy + r * c1o + (r + 1) * c1n) - o.Sx;
+    o.R0 = (m.R0 - dO.x) + dN.x;
+    o.Rx = (m.Rx - dO.y) + dN.y;
+    o.Ry = ((m.Ry + (double)r * dO.x) + (double)(r + 1) * dN.x) - o.R0;
+    return o;
+}
 
 // Column pass over rows base[0], base[stride], ..., base[2r * stride] of the
 // row-moment arrays (a/b as int2, s0/s1 as double2).

@@ -73,12 +73,12 @@ struct BatchFrame {
 };
 int front_tiles(int W, int H);
 int64_t merge_pairs(int W, int H);
-hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, int n, int rf,
-                              int *counter, int grid, hipStream_t s);
-hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off, int n,
-                              int64_t total, hipStream_t s);
-hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, int n, int rg, int th,
-                             int *counter, int grid, hipStream_t s);
+hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
+                              int n, int rf, int *counter, int grid, hipStream_t s);
+hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off,
+                              const int *block_frame, int n, int64_t total, hipStream_t s);
+hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
+                             int n, int rg, int th, int *counter, int grid, hipStream_t s);
 hipError_t launch_batch_reset(int *counters, int n_counters, const BatchFrame *frames, int n,
                               hipStream_t s);
 int back_tiles(int W, int H, int th);

@@ -70,19 +70,26 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     // ---- A: validity-coded input tile with halo R --------------------------
     // Labels (or the label forest) of this thread's outputs are fetched first so
     // their latency overlaps the LDS phases.
-    constexpr int kOutPerThread = TH > 0 ? (TH * kTileW + kBlock - 1) / kBlock : 1;
-    int32_t lab0[kOutPerThread];
+    // Outputs: thread (wave w, lane x) owns the vertical pairs of rows
+    // (2w + 8j, 2w + 8j + 1) of column x, j = 0, 1, ...
+    const int px_col = tid & 63, px_row = 2 * (tid >> 6);
+    constexpr int kPairs = TH > 0 ? (TH + 7) / 8 : 1;
+    int32_t lab0[2 * kPairs], labr[2 * kPairs];   // forest entries, their roots
     if (TH > 0) {
 #pragma unroll
-        for (int k = 0; k < kOutPerThread; ++k) {
-            const int e = tid + k * kBlock;
-            const int gx = x0 + (e & 63), gy = y0 + (e >> 6);
-            lab0[k] = -1;
-            if (rg > 0 && e < th * kTileW && gx < a.W && gy < a.H) {
-                if (a.forest) lab0[k] = a.forest[gy * a.W + gx];
-                else if (a.labels) lab0[k] = a.labels[(int64_t)gy * a.ld_lab + gx];
+        for (int j = 0; j < kPairs; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ty = px_row + 8 * j + h;
+                const int gx = x0 + px_col, gy = y0 + ty;
+                int32_t v = -1;
+                if (rg > 0 && ty < th && gx < a.W && gy < a.H) {
+                    if (a.forest) v = a.forest[gy * a.W + gx];
+                    else if (a.labels) v = a.labels[(int64_t)gy * a.ld_lab + gx];
+                }
+                lab0[2 * j + h] = v;
+                labr[2 * j + h] = v;
             }
-        }
     }
     if (RF >= 0 && RG >= 0 && TH > 0) {
         // static tile: issue every load before the first wait
@@ -98,6 +105,23 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
             v[k] = 0.0f;
             if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
                 v[k] = __builtin_nontemporal_load(a.src + (int64_t)gy * a.ld_src + gx);
+        }
+        // while the tile loads are in flight, resolve every owned pixel's
+        // forest entry to its root, all chains advancing together
+        if (rg > 0 && a.forest) {
+            bool again = true;
+            while (again) {
+                again = false;
+                int32_t nx[2 * kPairs];
+#pragma unroll
+                for (int k = 0; k < 2 * kPairs; ++k) nx[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
+#pragma unroll
+                for (int k = 0; k < 2 * kPairs; ++k)
+                    if (nx[k] != labr[k]) {
+                        labr[k] = nx[k];
+                        again = true;
+                    }
+            }
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
@@ -161,70 +185,90 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     if (rg == 0) return;
 
     // ---- C: anchored masked LSQ slope, A, normal, labels, records ------------
-    for (int e = tid; e < L.dtH * kTileW; e += kBlock) {
-        const int ly = e >> 6, tx = e & 63;
-        const RowMom m = row_moments<RG>(sDt + ly * L.dtW + tx, rg);
-        sAB[e] = make_int2(m.a, m.b);
-        sS[e] = make_double2(m.s0, m.s1);
+    // Roots found in this tile are counted in LDS and added to the global count
+    // once per tile: one contended atomic per workgroup instead of one per wave
+    // and row.
+    __shared__ int s_roots;
+    if (tid == 0) s_roots = 0;
+    // row moments: runs of 4 consecutive centres per thread (sliding window)
+    constexpr int kRun = 4;
+    for (int e = tid; e < L.dtH * (kTileW / kRun); e += kBlock) {
+        const int ly = e / (kTileW / kRun), tx0 = (e - ly * (kTileW / kRun)) * kRun;
+        row_moments_run<RG, kRun>(sDt + ly * L.dtW + tx0, rg, sAB + ly * kTileW + tx0,
+                                  sS + ly * kTileW + tx0);
     }
     __syncthreads();
-    for (int e = tid, k = 0; e < th * kTileW; e += kBlock, ++k) {
-        const int ty = e >> 6, tx = e & 63;   // one wave = one output row
-        const int gx = x0 + tx, gy = y0 + ty;
-        const bool in = gx < a.W && gy < a.H;
-        const float Dc = sDt[(ty + rg) * L.dtW + tx + rg];
-        float nx = __builtin_nanf(""), ny = nx, nz = nx, a1 = nx, a2 = nx;
-        if (in && Dc > 0.0f) {
-            const ColMom m = col_moments<RG, false>(sAB + e, sS + e, kTileW, rg);
-            double gu, gv;
-            if (slope_solve(m, Dc, a.need_g, gu, gv)) {
-                a1 = (float)(1.0 - gu);
-                a2 = (float)(-gv);
-                normal_from_slope(gu, gv, Dc, gx, gy, a.fx, a.fy, a.u0, a.v0, nx, ny, nz);
+    // column moments: the first row of a pair by direct sums, the second by
+    // sliding the window down one row
+    for (int j = 0; px_row + 8 * j < th; ++j) {
+        const int ty0 = px_row + 8 * j, tx = px_col;
+        const int eo = ty0 * kTileW + tx;
+        ColMom m = col_moments<RG, true>(sAB + eo, sS + eo, kTileW, rg);
+        for (int h = 0; h < 2; ++h) {
+            const int ty = ty0 + h;
+            if (h == 1) {
+                if (ty >= th) break;
+                m = col_slide(m, sAB + eo, sS + eo, kTileW, rg);
             }
-        }
-        int32_t lab = -1;
-        bool root = false;
-        int32_t first = -1;
-        if (in) {
-            if (TH > 0) first = lab0[k];
-            else if (a.forest) first = a.forest[gy * a.W + gx];
-            else if (a.labels) first = a.labels[(int64_t)gy * a.ld_lab + gx];
-        }
-        if (in && a.forest) {
-            const int x = gy * a.W + gx;
-            const int p = first;
-            if (p >= 0) {
-                lab = flat_find(a.forest, p);
-                root = lab == x;
-                if (a.labels == a.forest) {
-                    if (lab != p) a.forest[x] = lab;
+            const int gx = x0 + tx, gy = y0 + ty;
+            const bool in = gx < a.W && gy < a.H;
+            const float Dc = sDt[(ty + rg) * L.dtW + tx + rg];
+            float nx = __builtin_nanf(""), ny = nx, nz = nx, a1 = nx, a2 = nx;
+            if (in && Dc > 0.0f) {
+                double gu, gv;
+                if (slope_solve(m, Dc, a.need_g, gu, gv)) {
+                    a1 = (float)(1.0 - gu);
+                    a2 = (float)(-gv);
+                    normal_from_slope(gu, gv, Dc, gx, gy, a.fx, a.fy, a.u0, a.v0, nx, ny, nz);
                 }
             }
-            if (a.labels != a.forest) a.labels[(int64_t)gy * a.ld_lab + gx] = lab;
-        } else if (in && a.labels) {
-            lab = first;
+            int32_t lab = -1;
+            bool root = false;
+            int32_t first = -1;
+            if (in) {
+                if (TH > 0) first = lab0[2 * j + h];
+                else if (a.forest) first = a.forest[gy * a.W + gx];
+                else if (a.labels) first = a.labels[(int64_t)gy * a.ld_lab + gx];
+            }
+            if (in && a.forest) {
+                const int x = gy * a.W + gx;
+                const int p = first;
+                if (p >= 0) {
+                    lab = (RF >= 0 && RG >= 0 && TH > 0) ? labr[2 * j + h] : flat_find(a.forest, p);
+                    root = lab == x;
+                    if (a.labels == a.forest) {
+                        if (lab != p) a.forest[x] = lab;
+                    }
+                }
+                if (a.labels != a.forest) a.labels[(int64_t)gy * a.ld_lab + gx] = lab;
+            } else if (in && a.labels) {
+                lab = first;
+            }
+            if (a.count) {
+                const unsigned long long b = __ballot(root);
+                if ((tid & 63) == 0 && b) atomicAdd(&s_roots, (int)__popcll(b));
+            }
+            if (!in) continue;
+            const int64_t o = (int64_t)gy * a.ld_out + gx;
+            if (a.aff) {
+                a.aff[o] = a1;
+                a.aff[o + a.plane_out] = a2;
+            }
+            if (a.nrm) {
+                a.nrm[o] = nx;
+                a.nrm[o + a.plane_out] = ny;
+                a.nrm[o + 2 * a.plane_out] = nz;
+            }
+            if (a.rec) {
+                const snx_point p = make_point(gx, gy, Dc > 0.0f ? Dc : 0.0f, nx, ny, nz, lab,
+                                               a.fx, a.fy, a.b, a.u0, a.v0);
+                store_point(a.rec + (int64_t)gy * a.W + gx, p);
+            }
         }
-        if (a.count) {
-            const unsigned long long b = __ballot(root);
-            if ((tid & 63) == 0 && b) atomicAdd(a.count, (int)__popcll(b));
-        }
-        if (!in) continue;
-        const int64_t o = (int64_t)gy * a.ld_out + gx;
-        if (a.aff) {
-            a.aff[o] = a1;
-            a.aff[o + a.plane_out] = a2;
-        }
-        if (a.nrm) {
-            a.nrm[o] = nx;
-            a.nrm[o + a.plane_out] = ny;
-            a.nrm[o + 2 * a.plane_out] = nz;
-        }
-        if (a.rec) {
-            const snx_point p = make_point(gx, gy, Dc > 0.0f ? Dc : 0.0f, nx, ny, nz, lab,
-                                           a.fx, a.fy, a.b, a.u0, a.v0);
-            store_point(a.rec + (int64_t)gy * a.W + gx, p);
-        }
+    }
+    if (a.count) {
+        __syncthreads();
+        if (tid == 0 && s_roots) atomicAdd(a.count, s_roots);
     }
 }
 
@@ -239,27 +283,28 @@ k_stencil(StencilArgs a)
 // Persistent back stage over the (frame, tile) work list of a batch.
 template <int RG, int TH>
 __global__ void __launch_bounds__(kBlock)
-k_back_batch(const BatchFrame *frames, const int *tile_off, int n, int *counter)
+k_back_batch(const BatchFrame *frames, const int *tile_off, const int *tile_frame, int n,
+             int *counter)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ int item;
     const int total = tile_off[n];
-    while (true) {
-        if (threadIdx.x == 0) item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = item;
-        __syncthreads();
-        if (it >= total) break;
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tile_off[mid] <= it) lo = mid; else hi = mid - 1;
-        }
-        const StencilArgs a = frames[lo].back;
-        const int local = it - tile_off[lo];
+    if (threadIdx.x == 0) item = atomicAdd(counter, 1);
+    __syncthreads();
+    int it = item;
+    while (it < total) {
+        // the next item is claimed now, so the atomic's latency overlaps this tile
+        int nxt = 0;
+        if (threadIdx.x == 0) nxt = atomicAdd(counter, 1);
+        const int f = tile_frame[it];
+        const StencilArgs a = frames[f].back;
+        const int local = it - tile_off[f];
         const int tx = (a.W + kTileW - 1) / kTileW;
         stencil_tile<0, RG, TH>(a, local % tx, local / tx, smem);
         __syncthreads();
+        if (threadIdx.x == 0) item = nxt;
+        __syncthreads();
+        it = item;
     }
 }
 
@@ -298,7 +343,7 @@ size_t stencil_lds_bytes(int rf, int rg, int th) { return make_layout(rf, rg, th
 
 int back_tiles(int W, int H, int th) { return ((W + kTileW - 1) / kTileW) * ((H + th - 1) / th); }
 
-using BatchFn = void (*)(const BatchFrame *, const int *, int, int *);
+using BatchFn = void (*)(const BatchFrame *, const int *, const int *, int, int *);
 struct BatchInst { int rg, th; BatchFn fn; };
 constexpr BatchInst kBatchInst[] = {
     {1, 16, &k_back_batch<1, 16>}, {2, 16, &k_back_batch<2, 16>}, {3, 16, &k_back_batch<3, 16>},
@@ -315,13 +360,13 @@ bool batch_has_instance(int rg, int th)
     return false;
 }
 
-hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, int n, int rg, int th,
-                             int *counter, int grid, hipStream_t s)
+hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
+                             int n, int rg, int th, int *counter, int grid, hipStream_t s)
 {
     for (const BatchInst &i : kBatchInst)
         if (i.rg == rg && i.th == th) {
             hipLaunchKernelGGL(i.fn, dim3(grid), dim3(kBlock), stencil_lds_bytes(0, rg, th), s,
-                               frames, tile_off, n, counter);
+                               frames, tile_off, tile_frame, n, counter);
             return hipGetLastError();
         }
     return hipErrorInvalidValue;
