@@ -296,7 +296,9 @@ k_back_batch(const BatchFrame *frames, const int *tile_off, const int *tile_fram
         // the next item is claimed now, so the atomic's latency overlaps this tile
         int nxt = 0;
         if (threadIdx.x == 0) nxt = atomicAdd(counter, 1);
-        const int f = tile_frame[it];
+        // uniform across the workgroup: keep the index and the arguments in
+        // scalar registers
+        const int f = __builtin_amdgcn_readfirstlane(tile_frame[__builtin_amdgcn_readfirstlane(it)]);
         const StencilArgs a = frames[f].back;
         const int local = it - tile_off[f];
         const int tx = (a.W + kTileW - 1) / kTileW;
