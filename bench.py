@@ -59,6 +59,10 @@ def parse():
                     help="distinct generated road frames (the rest are copies)")
     ap.add_argument("--uneven-frames", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--iso-sweep", action="store_true",
+                    help="instead of the bench line: mean angular error and Mpixel/s of the plain "
+                         "path over filter x gradient windows and of the learned path over "
+                         "gradient windows, on held-out road frames (markdown table)")
     return ap.parse_args()
 
 
@@ -196,8 +200,68 @@ def traffic_from_profiles(kernel_name):
     return float(m_b.group(1)) if ok else None
 
 
+def iso_sweep(args):
+    """Error/throughput of the plain and learned paths on 2048x1024 road frames
+    (seeds 5200, 5201; per-frame snx_pipeline calls, inputs resident)."""
+    import numpy as np
+    import torch
+    import paper_2504_15121_amd as snx
+    from paper_2504_15121_amd import learned
+    from synth import scenes
+    snx.load()
+    dev = torch.device("cuda:0")
+    frames = [scenes.road_scene(seed=5200 + i) for i in range(2)]
+    H, W = frames[0].disp.shape
+    ck = learned.load_checkpoint(learned.DEFAULT_MODEL)
+    P = torch.from_numpy(ck["params"]).to(dev)
+    packed = torch.empty(snx.snx_cnn_packed_bytes() // 2, dtype=torch.int16, device=dev)
+    snx.snx_cnn_pack(P, packed)
+    cws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=dev)
+    model = snx.cnn_model(P, packed, cws)
+    d = [torch.from_numpy(f.disp).to(dev) for f in frames]
+    lab = torch.empty((H, W), dtype=torch.int32, device=dev)
+    pts = torch.empty((H, W, 8), device=dev)
+    ws = torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8, device=dev)
+
+    def run(k, nf, ng, cnn):
+        snx.snx_pipeline(d[k], frames[k].cam, lab, pts, ws, filter_window=nf, normal_window=ng,
+                         cnn=cnn)
+
+    def timed(nf, ng, cnn, n=10):
+        for _ in range(3):
+            run(0, nf, ng, cnn)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            run(0, nf, ng, cnn)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    print("| path | n_f | n_g | mean angular error (deg) | ms per frame | Mpixel/s |")
+    print("|---|---|---|---|---|---|")
+    for ng in (9, 15, 21, 31, 45, 61):
+        for nf, cnn in ((1, None), (3, None), (5, None), (9, None), (3, model)):
+            snx.snx_autotune(W, H, filter_window=nf if cnn is None else 1, normal_window=ng)
+            es, ec = 0.0, 0
+            for k in range(len(frames)):
+                run(k, nf, ng, cnn)
+                torch.cuda.synchronize()
+                e, c = angular_error_sum(pts.cpu().numpy(), frames[k].normal)
+                es, ec = es + e, ec + c
+            ms = timed(nf, ng, cnn)
+            tag = "learned" if cnn is not None else "plain"
+            print(f"| {tag} | {'cnn' if cnn is not None else nf} | {ng} | {es / ec:.3f} | "
+                  f"{ms:.4f} | {W * H / (ms * 1e-3) / 1e6:.0f} |", flush=True)
+
+
 def main():
     args = parse()
+    if args.iso_sweep:
+        iso_sweep(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
