@@ -1,26 +1,28 @@
 // Learned denoiser inference with all six convolutions fused in one kernel.
 //
-// A workgroup owns a 16 x 16 output tile at a time and keeps every
+// A workgroup owns a 24 x 24 output tile at a time and keeps every
 // intermediate activation in LDS: layer k's output is computed on the region
-// the remaining layers need (26, 24, 22, 20, 18 pixels square for layers 1..5,
-// 16 for layer 6), so nothing but the disparity, the LSQ filter mu and D~
+// the remaining layers need (34, 32, 30, 28, 26 pixels square for layers 1..5,
+// 24 for layer 6), so nothing but the disparity, the LSQ filter mu and D~
 // touches HBM.  Region pixels outside the image are set to zero after every
 // layer, which is the zero padding of each convolution.
 //
 // The kernel is persistent (one 512-thread workgroup per CU walks the tiles)
 // and pipelined: each layer's weights are copied once per workgroup from
-// global memory into one of two LDS buffers while the previous layer computes
-// (instead of every wave fetching them from L2), and the next tile's disparity
-// and mu are fetched into registers during the current tile's last layers.
+// global memory into LDS (fetched into registers during the previous layer,
+// stored once every wave has taken the previous layer's weights into its
+// registers), and the next tile's disparity and mu are fetched into registers
+// during the current tile's last layers.  LDS bandwidth is the limit of this
+// kernel, which is why the tile is as large as the 160 KB allow.
 //
 // MFMA orientation (v_mfma_f32_16x16x32_bf16): A = weights (16 output channels
 // x 32 inputs), B = activations (32 inputs x 16 pixels), so that a lane's four
 // results are four consecutive output channels of one pixel.  The 16 pixels of
 // a B operand are 16 consecutive pixels of the row-major output region.
-// Activations are NHWC bf16, 32 channels in 64 bytes, at a pitch of 80 bytes a
-// pixel (weights: 80 bytes a row of 32 inputs): the 16 lanes of a
-// quarter-wave then hit 16 distinct 16-byte bank groups, and every tap's
-// address is the group's base plus an immediate offset.
+// Activations are NHWC bf16, 32 channels in 64 bytes a pixel, with the four
+// 16-byte channel chunks of pixel p stored at chunk c ^ ((p >> 1) & 3), so the
+// 8 lanes served together by a 16-byte LDS read (8 consecutive pixels, one
+// chunk) hit 8 distinct bank groups; weight rows are swizzled the same way.
 //
 // The arithmetic per output is that of the layer-by-layer kernels (same taps in
 // the same order, same MFMA, bias added to the FP32 sum, ReLU, bf16 RNE).
@@ -37,27 +39,25 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFT = 16;                 // output tile edge
+constexpr int kFT = 24;                 // output tile edge
 constexpr int kRA = kFT + 10;           // largest region held in buffer A (layer 1 output)
 constexpr int kRB = kFT + 8;            // largest region held in buffer B (layer 2 output)
 constexpr int kRF = kFT + 12;           // feature region (layer 1 input)
 constexpr int kWaves = 8;               // waves per workgroup
 constexpr int kThreads = kWaves * 64;
-constexpr int kPitch = 80;              // LDS bytes per activation pixel / weight row
 
-// One layer's weights in LDS: up to 9 x 32 rows of 32 bf16 at kPitch, then
+// One layer's weights in LDS: up to 9 x 32 rows of 32 bf16 (64 bytes), then
 // 32 float biases.
 constexpr int kWRows = 9 * 32;
-constexpr int kWBias = kWRows * kPitch;                 // 23040
-constexpr int kWBuf = kWBias + 32 * 4;                  // 23168
+constexpr int kWBias = kWRows * 64;                     // 18432
+constexpr int kWBuf = kWBias + 32 * 4;                  // 18560
 constexpr int kLdsA = 0;
-constexpr int kLdsB = kLdsA + kRA * kRA * kPitch;       // 54080
-constexpr int kLdsW0 = kLdsB + kRB * kRB * kPitch;      // 100160
-constexpr int kLdsW1 = kLdsW0 + kWBuf;                  // 123328
-constexpr size_t kFusedLds = kLdsW1 + kWBuf;            // 146496 bytes
+constexpr int kLdsB = kLdsA + kRA * kRA * 64;           // 73984
+constexpr int kLdsW = kLdsB + kRB * kRB * 64;           // 139520
+constexpr size_t kFusedLds = kLdsW + kWBuf;             // 158080 bytes
 
-// feature pixels per thread (28 x 28 region over 512 threads)
-constexpr int kFeatPer = (kRF * kRF + kThreads - 1) / kThreads;   // 2
+// feature pixels per thread (36 x 36 region over 512 threads)
+constexpr int kFeatPer = (kRF * kRF + kThreads - 1) / kThreads;   // 3
 
 __device__ __forceinline__ uint16_t bf16_rne(float f)
 {
@@ -79,14 +79,20 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-__device__ __forceinline__ u32x4 lds16(const unsigned char *p) { return *reinterpret_cast<const u32x4 *>(p); }
+// byte offset of 16-byte chunk c of pixel (or weight row) p
+__device__ __forceinline__ int chunk_off(int p, int c) { return p * 64 + ((c ^ ((p >> 1) & 3)) << 4); }
+
+__device__ __forceinline__ u32x4 lds16(const unsigned char *base, int p, int c)
+{
+    return *reinterpret_cast<const u32x4 *>(base + chunk_off(p, c));
+}
 
 // ---------------------------------------------------------------------------
 // Weight staging.  Stage s = 1..6 is layer s.  Its packed weights are
 // contiguous rows of 32 bf16 (64 bytes): 32 rows (layer 1), 9 x 32 (layers
 // 2..5), 9 x 16 (layer 6).  Thread t holds 16-byte chunks t, t + 512, t + 1024
-// of the rows in registers and, one stage later, writes them to LDS at pitch
-// kPitch; threads 0..7 also carry the bias (one float for layer 6).
+// of the rows in registers until they are written to LDS; threads 0..7 also
+// carry the bias (one float for layer 6).
 // ---------------------------------------------------------------------------
 struct StageRegs {
     u32x4 c[3];
@@ -119,10 +125,19 @@ __device__ __forceinline__ void stage_store(unsigned char *wbuf, int s, int tid,
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const int c = tid + k * kThreads;
-        if (c < nchunks) *reinterpret_cast<u32x4 *>(wbuf + (c >> 2) * kPitch + ((c & 3) << 4)) = r.c[k];
+        if (c < nchunks) *reinterpret_cast<u32x4 *>(wbuf + chunk_off(c >> 2, c & 3)) = r.c[k];
     }
     if ((s < 6 && tid < 8) || (s == 6 && tid == 0))
         *reinterpret_cast<u32x4 *>(wbuf + kWBias + tid * 16) = r.bias;
+}
+
+__device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, float (&bl)[2][4])
+{
+    const float *b = reinterpret_cast<const float *>(wbuf + kWBias);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bl[mb][j] = b[mb * 16 + 4 * q + j];
 }
 
 // ---------------------------------------------------------------------------
@@ -147,57 +162,39 @@ __device__ __forceinline__ void store_act(unsigned char *out, int p, int q, bool
         w[2 * mb + 1] = inside ? pack_bf16(v[2], v[3]) : 0u;
     }
     // channels 4q.. sit in chunk q/2 (half q&1); channels 16+4q.. in chunk 2 + q/2
-    unsigned char *px = out + p * kPitch + ((q & 1) << 3);
-    *reinterpret_cast<uint2 *>(px + ((q >> 1) << 4)) = make_uint2(w[0], w[1]);
-    *reinterpret_cast<uint2 *>(px + ((2 + (q >> 1)) << 4)) = make_uint2(w[2], w[3]);
+    *reinterpret_cast<uint2 *>(out + chunk_off(p, q >> 1) + ((q & 1) << 3)) = make_uint2(w[0], w[1]);
+    *reinterpret_cast<uint2 *>(out + chunk_off(p, 2 + (q >> 1)) + ((q & 1) << 3)) =
+        make_uint2(w[2], w[3]);
 }
 
-__device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, float (&bl)[2][4])
-{
-    const float *b = reinterpret_cast<const float *>(wbuf + kWBias);
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bl[mb][j] = b[mb * 16 + 4 * q + j];
-}
-
-// One 32 -> 32 layer from region RIN (`in`) to region RIN - 2 (`out`), weights
-// in `wbuf`.  (ox, oy): image coordinates of the output region's first pixel.
+// One 32 -> 32 layer from region RIN (`in`) to region RIN - 2 (`out`) with the
+// weights already in registers.  (ox, oy): image coordinates of the output
+// region's first pixel.
 template <int RIN>
 __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char *out,
-                                          const unsigned char *wbuf, int ox, int oy, int W, int H,
-                                          int lane, int wave)
+                                          const u32x4 (&wa)[9][2], const float (&bs)[2][4],
+                                          int ox, int oy, int W, int H, int lane, int wave)
 {
     constexpr int RO = RIN - 2;
     constexpr int NP = RO * RO;
     constexpr int NG = (NP + 15) / 16;
     const int q = lane >> 4, col = lane & 15;
-    u32x4 wa[9][2];
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) wa[t][mb] = lds16(wbuf + (t * 32 + mb * 16 + col) * kPitch + q * 16);
-    float bs[2][4];
-    load_bias(wbuf, q, bs);
-
     // two groups (g, g + kWaves) per iteration: four independent accumulator chains
     for (int g = wave; g < NG; g += 2 * kWaves) {
-        int p[2], x[2], y[2];
-        const unsigned char *src[2];
+        int p[2], x[2], y[2], base[2];
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             p[k] = (g + kWaves * k) * 16 + col;
             const int pc = p[k] < NP ? p[k] : NP - 1;
             y[k] = pc / RO;
             x[k] = pc - y[k] * RO;
-            src[k] = in + ((y[k] + 1) * RIN + x[k] + 1) * kPitch + q * 16;
+            base[k] = (y[k] + 1) * RIN + x[k] + 1;
         }
         u32x4 bv[2][9];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
-                bv[k][t] = lds16(src[k] + ((t / 3 - 1) * RIN + (t % 3 - 1)) * kPitch);
+            for (int t = 0; t < 9; ++t) bv[k][t] = lds16(in, base[k] + (t / 3 - 1) * RIN + (t % 3 - 1), q);
         f32x4 acc[2][2];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -218,6 +215,16 @@ __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char
             }
         }
     }
+}
+
+__device__ __forceinline__ void load_mid_weights(const unsigned char *wbuf, int q, int col,
+                                                 u32x4 (&wa)[9][2], float (&bs)[2][4])
+{
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) wa[t][mb] = lds16(wbuf, t * 32 + mb * 16 + col, q);
+    load_bias(wbuf, q, bs);
 }
 
 // Disparity and mu of the feature pixels this thread builds, for tile (tx, ty).
@@ -247,8 +254,7 @@ k_cnn_fused(CnnFusedArgs a)
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned char *bufA = smem + kLdsA;
     unsigned char *bufB = smem + kLdsB;
-    unsigned char *wb0 = smem + kLdsW0;
-    unsigned char *wb1 = smem + kLdsW1;
+    unsigned char *wbuf = smem + kLdsW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, col = lane & 15;
     const int W = a.W, H = a.H;
@@ -261,12 +267,14 @@ k_cnn_fused(CnnFusedArgs a)
     feat_fetch(a, tile % ntx, tile / ntx, tid, f);
     StageRegs r;
     stage_fetch(a, 1, tid, r);
-    stage_store(wb1, 1, tid, r);          // layer 1 always comes from buffer 1
+    stage_store(wbuf, 1, tid, r);
 
+    u32x4 wa[9][2];
+    float bs[2][4];
     while (true) {
         const int tx = tile % ntx, ty = tile / ntx;
         const int x0 = tx * kFT, y0 = ty * kFT;
-        // ---- features over the 28 x 28 region at (x0-6, y0-6): (x0 bf16, valid bf16)
+        // ---- features over the 36 x 36 region at (x0-6, y0-6): (x0 bf16, valid bf16)
         uint32_t *feat = reinterpret_cast<uint32_t *>(bufB);
 #pragma unroll
         for (int k = 0; k < kFeatPer; ++k) {
@@ -278,16 +286,17 @@ k_cnn_fused(CnnFusedArgs a)
             }
         }
         stage_fetch(a, 2, tid, r);
-        __syncthreads();
+        __syncthreads();                                  // features and layer-1 weights ready
 
         // ---- layer 1: 2 -> 32, K slots = tap * 2 + channel (18 used)
         {
-            constexpr int RO = kRA, NP = RO * RO, NG = (NP + 15) / 16;
-            u32x4 wa[2];
+            u32x4 w1[2];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) wa[mb] = lds16(wb1 + (mb * 16 + col) * kPitch + q * 16);
-            float bs[2][4];
-            load_bias(wb1, q, bs);
+            for (int mb = 0; mb < 2; ++mb) w1[mb] = lds16(wbuf, mb * 16 + col, q);
+            load_bias(wbuf, q, bs);
+            __syncthreads();                              // every wave holds layer 1's weights
+            stage_store(wbuf, 2, tid, r);
+            constexpr int RO = kRA, NP = RO * RO, NG = (NP + 15) / 16;
             for (int g = wave; g < NG; g += kWaves) {
                 const int p = g * 16 + col;
                 const int pc = p < NP ? p : NP - 1;
@@ -301,66 +310,81 @@ k_cnn_fused(CnnFusedArgs a)
                     bv[i] = v;
                 }
                 const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 a0 = mfma(wa[0], bv, z), a1 = mfma(wa[1], bv, z);
+                const f32x4 a0 = mfma(w1[0], bv, z), a1 = mfma(w1[1], bv, z);
                 if (p < NP) {
                     const int gx = x0 - 5 + x, gy = y0 - 5 + y;
                     store_act(bufA, p, q, gx >= 0 && gx < W && gy >= 0 && gy < H, a0, a1, bs);
                 }
             }
         }
-        stage_store(wb0, 2, tid, r);
-        __syncthreads();
+        __syncthreads();                                  // layer 1 out and layer-2 weights ready
         stage_fetch(a, 3, tid, r);
-        mid_layer<kRA>(bufA, bufB, wb0, x0 - 4, y0 - 4, W, H, lane, wave);
-        stage_store(wb1, 3, tid, r);
+        load_mid_weights(wbuf, q, col, wa, bs);
+        __syncthreads();
+        stage_store(wbuf, 3, tid, r);
+        mid_layer<kRA>(bufA, bufB, wa, bs, x0 - 4, y0 - 4, W, H, lane, wave);
         __syncthreads();
         stage_fetch(a, 4, tid, r);
-        mid_layer<kRB>(bufB, bufA, wb1, x0 - 3, y0 - 3, W, H, lane, wave);
-        stage_store(wb0, 4, tid, r);
+        load_mid_weights(wbuf, q, col, wa, bs);
+        __syncthreads();
+        stage_store(wbuf, 4, tid, r);
+        mid_layer<kRB>(bufB, bufA, wa, bs, x0 - 3, y0 - 3, W, H, lane, wave);
         __syncthreads();
         stage_fetch(a, 5, tid, r);
-        mid_layer<kRB - 2>(bufA, bufB, wb0, x0 - 2, y0 - 2, W, H, lane, wave);
-        stage_store(wb1, 5, tid, r);
+        load_mid_weights(wbuf, q, col, wa, bs);
+        __syncthreads();
+        stage_store(wbuf, 5, tid, r);
+        mid_layer<kRB - 2>(bufA, bufB, wa, bs, x0 - 2, y0 - 2, W, H, lane, wave);
         __syncthreads();
         stage_fetch(a, 6, tid, r);
         const int next = tile + gridDim.x;
         if (next < ntiles) feat_fetch(a, next % ntx, next / ntx, tid, f);
-        mid_layer<kRB - 4>(bufB, bufA, wb1, x0 - 1, y0 - 1, W, H, lane, wave);
-        stage_store(wb0, 6, tid, r);
+        load_mid_weights(wbuf, q, col, wa, bs);
+        __syncthreads();
+        stage_store(wbuf, 6, tid, r);
+        mid_layer<kRB - 4>(bufB, bufA, wa, bs, x0 - 1, y0 - 1, W, H, lane, wave);
         __syncthreads();
         stage_fetch(a, 1, tid, r);
 
-        // ---- layer 6: 32 -> 1 on the 16 x 16 tile; rows wave and wave + 8
+        // ---- layer 6: 32 -> 1 on the 24 x 24 tile, 16 consecutive pixels per group
         {
-            constexpr int RIN = kFT + 2;
-            u32x4 wa[9];
+            constexpr int RIN = kFT + 2, NP = kFT * kFT, NG = NP / 16;
+            u32x4 w6[9];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) wa[t] = lds16(wb0 + (t * 16 + col) * kPitch + q * 16);
-            const float b6 = reinterpret_cast<const float *>(wb0 + kWBias)[0];
-            u32x4 bv[2][9];
+            for (int t = 0; t < 9; ++t) w6[t] = lds16(wbuf, t * 16 + col, q);
+            const float b6 = reinterpret_cast<const float *>(wbuf + kWBias)[0];
+            __syncthreads();                              // every wave holds layer 6's weights
+            stage_store(wbuf, 1, tid, r);
+            for (int g = wave; g < NG; g += 2 * kWaves) {
+                int p[2], x[2], y[2];
+                u32x4 bv[2][9];
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const unsigned char *src = bufA + ((wave + kWaves * k + 1) * RIN + col + 1) * kPitch + q * 16;
+                for (int k = 0; k < 2; ++k) {
+                    const int gg = g + kWaves * k;
+                    p[k] = (gg < NG ? gg : NG - 1) * 16 + col;
+                    y[k] = p[k] / kFT;
+                    x[k] = p[k] - y[k] * kFT;
+                    const int base = (y[k] + 1) * RIN + x[k] + 1;
 #pragma unroll
-                for (int t = 0; t < 9; ++t) bv[k][t] = lds16(src + ((t / 3 - 1) * RIN + (t % 3 - 1)) * kPitch);
-            }
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                    for (int t = 0; t < 9; ++t) bv[k][t] = lds16(bufA, base + (t / 3 - 1) * RIN + (t % 3 - 1), q);
+                }
+                f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
+                for (int t = 0; t < 9; ++t)
 #pragma unroll
-                for (int k = 0; k < 2; ++k) acc[k] = mfma(wa[t], bv[k][t], acc[k]);
-            // output channel 0 of pixel col sits in lanes q == 0, element 0
+                    for (int k = 0; k < 2; ++k) acc[k] = mfma(w6[t], bv[k][t], acc[k]);
+                // output channel 0 of each pixel sits in lanes q == 0, element 0
 #pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int gx = x0 + col, gy = y0 + wave + kWaves * k;
-                if (q == 0 && gx < W && gy < H) {
-                    const float mu = a.mu[(int64_t)gy * W + gx];
-                    const float yv = acc[k][0] + b6;
-                    a.out[(int64_t)gy * a.ld_out + gx] = (mu == mu) ? mu + a.s * yv : __builtin_nanf("");
+                for (int k = 0; k < 2; ++k) {
+                    const int gx = x0 + x[k], gy = y0 + y[k];
+                    if (q == 0 && g + kWaves * k < NG && gx < W && gy < H) {
+                        const float mu = a.mu[(int64_t)gy * W + gx];
+                        const float yv = acc[k][0] + b6;
+                        a.out[(int64_t)gy * a.ld_out + gx] = (mu == mu) ? mu + a.s * yv : __builtin_nanf("");
+                    }
                 }
             }
         }
-        stage_store(wb1, 1, tid, r);
         __syncthreads();
         if (next >= ntiles) break;
         tile = next;
