@@ -348,10 +348,12 @@ typedef struct snx_plan snx_plan;
 
 /* Validates every frame, picks the tile height (the autotuned one for the
  * largest frame's size class, tuning it now if snx_autotune has not run for
- * that class), allocates the device frame table and
- * any per-frame scratch (a label forest when label_stride != width, the
- * filtered plane when disp_dn is NULL).  The filter window must be 1 or 3, or
- * mode SNX_FILTER_CNN with a model whose workspace fits the largest frame.
+ * that class), allocates the device frame table and any per-frame scratch (a
+ * label forest when label_stride != width, the filtered plane when disp_dn is
+ * NULL, and with the learned filter the network's input filter plane mu).
+ * The filter window must be 1 or 3, or mode SNX_FILTER_CNN with a model whose
+ * params and packed weights are set (its workspace is not used: the network
+ * runs over the tiles of every frame in one launch).
  * A set-up call (allocates, synchronizes). */
 snx_status snx_plan_create(const snx_frame *frames, int32_t n,
                            const snx_denoise_params *denoise,

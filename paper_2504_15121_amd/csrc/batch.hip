@@ -3,17 +3,19 @@
 // launches captured once in a hipGraph and replayed on every run.
 //
 //   reset   zero the two work counters and every frame's component count
-//   [learned filter: the network per frame]
-//   front   persistent workgroups fetch (frame, tile) items: filter + local forest
+//   front   persistent workgroups fetch (frame, tile) items: 3x3 filter + local
+//           forest (with the learned filter: the 3x3 filter is the network's mu)
 //   merge   one thread per tile-seam pair of every frame
+//   [cnn    learned filter: the fused network over the tiles of every frame]
 //   back    persistent workgroups fetch (frame, tile) items: gradients, A,
 //           normals, label resolution, point records
 #include <math.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <vector>
 
-#include "snx_internal.hpp"
+#include "snx_cnn.hpp"
 
 namespace snx {
 snx_status api_fail(snx_status st, const char *msg);
@@ -29,6 +31,10 @@ struct snx_plan {
     snx::BatchFrame *d_frames = nullptr;
     int *d_front_off = nullptr, *d_back_off = nullptr, *d_counters = nullptr;
     int *d_front_frame = nullptr, *d_back_frame = nullptr, *d_merge_frame = nullptr;
+    snx::CnnFusedArgs cnn_common{};                 // params and packed weights
+    snx::CnnFusedArgs *d_cnn = nullptr;             // per-frame network arguments
+    int *d_cnn_off = nullptr, *d_cnn_frame = nullptr;
+    int cnn_total = 0;
     int64_t *d_seam_off = nullptr;
     int64_t seam_total = 0;
     int grid_front = 1, grid_back = 1;
@@ -54,6 +60,9 @@ void release(snx_plan *p)
     (void)hipFree(p->d_back_off);
     (void)hipFree(p->d_seam_off);
     (void)hipFree(p->d_counters);
+    (void)hipFree(p->d_cnn);
+    (void)hipFree(p->d_cnn_off);
+    (void)hipFree(p->d_cnn_frame);
     (void)hipFree(p->d_front_frame);
     (void)hipFree(p->d_back_frame);
     (void)hipFree(p->d_merge_frame);
@@ -64,19 +73,17 @@ hipError_t enqueue(snx_plan *p, hipStream_t s)
 {
     hipError_t e = snx::launch_batch_reset(p->d_counters, 2, p->d_frames, p->n, s);
     if (e != hipSuccess) return e;
-    if (p->cnn) {
-        for (int i = 0; i < p->n; ++i) {
-            const snx::BatchFrame &f = p->host[i];
-            if (snx_cnn_denoise(f.front.D, f.front.ld, f.front.W, f.front.H, &p->model,
-                                const_cast<float *>(f.back.src), f.back.ld_src, s) != SNX_OK)
-                return hipErrorLaunchFailure;
-        }
-    }
-    if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->d_front_frame, p->n, p->rf,
-                                     p->d_counters, p->grid_front, s)) != hipSuccess)
+    // the front filters with window 3 also for the learned filter (its mu)
+    if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->d_front_frame, p->n,
+                                     p->cnn ? 1 : p->rf, p->d_counters, p->grid_front, s)) !=
+        hipSuccess)
         return e;
     if ((e = snx::launch_batch_merge(p->d_frames, p->d_seam_off, p->d_merge_frame, p->n,
                                      p->seam_total, s)) != hipSuccess)
+        return e;
+    if (p->cnn &&
+        (e = snx::cnn_forward_fused_batch(p->cnn_common, p->d_cnn, p->d_cnn_off, p->d_cnn_frame,
+                                          p->n, p->cnn_total, s)) != hipSuccess)
         return e;
     return snx::launch_batch_back(p->d_frames, p->d_back_off, p->d_back_frame, p->n, p->rg, p->th,
                                   p->d_counters + 1, p->grid_back, s);
@@ -99,8 +106,10 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         return api_fail(SNX_ERR_UNSUPPORTED, "batch plans filter with window 1 or 3");
     if (cnn) {
         const snx_cnn_model *m = static_cast<const snx_cnn_model *>(dp->model);
-        if (!m || !m->params || !m->packed || !m->workspace)
-            return api_fail(SNX_ERR_MODEL, "CNN filter needs a complete model");
+        if (!m || !m->params || !m->packed)
+            return api_fail(SNX_ERR_MODEL, "CNN filter needs the model's params and packed weights");
+        if (((uintptr_t)m->params & 15) || ((uintptr_t)m->packed & 15))
+            return api_fail(SNX_ERR_ARG, "model buffers must be 16-byte aligned");
     }
     if (np->window < 3 || np->window % 2 == 0 || np->window > snx::kMaxWindow)
         return api_fail(SNX_ERR_ARG, "gradient window must be odd, 3..63");
@@ -119,9 +128,6 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         if (!(isfinite(c.fx) && c.fx > 0 && isfinite(c.fy) && c.fy > 0 && isfinite(c.baseline) &&
               c.baseline > 0 && isfinite(c.u0) && isfinite(c.v0)))
             return api_fail(SNX_ERR_ARG, "frame camera");
-        if (cnn && snx_cnn_workspace_size(f.width, f.height, 1, 0) >
-                       static_cast<const snx_cnn_model *>(dp->model)->workspace_bytes)
-            return api_fail(SNX_ERR_WORKSPACE, "CNN workspace too small for a frame");
         if ((int64_t)f.width * f.height > (int64_t)maxW * maxH) { maxW = f.width; maxH = f.height; }
     }
     const int need_g = np->min_support > 0 ? np->min_support : (np->window * np->window + 1) / 2;
@@ -146,7 +152,8 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
     p->rg = rg;
     p->th = th;
     p->host.resize(n);
-    std::vector<int> foff(n + 1, 0), boff(n + 1, 0);
+    std::vector<int> foff(n + 1, 0), boff(n + 1, 0), coff(n + 1, 0);
+    std::vector<snx::CnnFusedArgs> cnn_args(cnn ? n : 0);
     std::vector<int64_t> soff(n + 1, 0);
     hipError_t e = hipSuccess;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
@@ -167,6 +174,14 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
             dn = static_cast<float *>(q);
             ld_dn = f.width;
         }
+        // the learned filter's mu (3x3 LSQ filter, support 3) written by the front
+        float *mu = nullptr;
+        if (cnn && e == hipSuccess) {
+            void *q = nullptr;
+            e = hipMalloc(&q, (size_t)f.width * f.height * 4);
+            if (e == hipSuccess) p->owned.push_back(q);
+            mu = static_cast<float *>(q);
+        }
         snx::BatchFrame &b = p->host[i];
         memset(&b, 0, sizeof b);
         b.front.D = f.disp;
@@ -175,10 +190,24 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         b.front.H = f.height;
         b.front.k_rel = cp->k_rel;
         b.front.t_abs = cp->t_abs;
-        b.front.rf = p->rf;
-        b.front.need_f = dp->min_support > 3 ? dp->min_support : 3;
-        b.front.dn = cnn ? nullptr : dn;
-        b.front.ld_dn = ld_dn;
+        b.front.rf = cnn ? 1 : p->rf;
+        b.front.need_f = cnn ? 3 : (dp->min_support > 3 ? dp->min_support : 3);
+        b.front.dn = cnn ? mu : dn;
+        b.front.ld_dn = cnn ? f.width : ld_dn;
+        if (cnn) {
+            snx::CnnFusedArgs &c = cnn_args[i];
+            memset(&c, 0, sizeof c);
+            c.W = f.width;
+            c.H = f.height;
+            c.D = f.disp;
+            c.ldD = f.stride;
+            c.mu = mu;
+            c.params = p->model.params;
+            c.packed = static_cast<const uint16_t *>(p->model.packed);
+            c.out = dn;
+            c.ld_out = ld_dn;
+            c.s = snx::kCnnScale;
+        }
         b.front.forest = forest;
         b.front.count = f.num_components;
         b.back.src = dn;
@@ -200,15 +229,17 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         b.back.rec = f.points;
         b.back.th = th;
         foff[i + 1] = foff[i] + snx::front_tiles(f.width, f.height);
+        coff[i + 1] = coff[i] + (cnn ? snx::cnn_fused_tiles(f.width, f.height) : 0);
         boff[i + 1] = boff[i] + snx::back_tiles(f.width, f.height, th);
         soff[i + 1] = soff[i] + snx::merge_pairs(f.width, f.height);
     }
     // item -> frame tables (front tiles, back tiles) and the frame of each
     // merge block's first seam pair
-    std::vector<int> front_frame(foff[n]), back_frame(boff[n]);
+    std::vector<int> front_frame(foff[n]), back_frame(boff[n]), cnn_frame(coff[n]);
     for (int i = 0; i < n; ++i) {
         for (int t = foff[i]; t < foff[i + 1]; ++t) front_frame[t] = i;
         for (int t = boff[i]; t < boff[i + 1]; ++t) back_frame[t] = i;
+        for (int t = coff[i]; t < coff[i + 1]; ++t) cnn_frame[t] = i;
     }
     const int64_t merge_blocks = (soff[n] + 255) / 256;
     std::vector<int> merge_frame((size_t)(merge_blocks > 0 ? merge_blocks : 1), 0);
@@ -225,6 +256,16 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
     upload(&p->d_front_frame, front_frame);
     upload(&p->d_back_frame, back_frame);
     upload(&p->d_merge_frame, merge_frame);
+    if (cnn) {
+        upload(&p->d_cnn_off, coff);
+        upload(&p->d_cnn_frame, cnn_frame);
+        if (e == hipSuccess) e = hipMalloc(&p->d_cnn, sizeof(snx::CnnFusedArgs) * n);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_cnn, cnn_args.data(), sizeof(snx::CnnFusedArgs) * n,
+                          hipMemcpyHostToDevice);
+        p->cnn_total = coff[n];
+        p->cnn_common = cnn_args[0];
+    }
     if (e == hipSuccess) e = hipMalloc(&p->d_frames, sizeof(snx::BatchFrame) * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_front_off, sizeof(int) * (n + 1));
     if (e == hipSuccess) e = hipMalloc(&p->d_back_off, sizeof(int) * (n + 1));

@@ -248,8 +248,31 @@ __device__ __forceinline__ void feat_fetch(const CnnFusedArgs &a, int tx, int ty
     }
 }
 
+// Item `item` of the work: a tile of the single frame `a0`, or (BATCH) a tile of
+// frame tile_frame[item] of `frames`.  The item and frame index are uniform
+// across the workgroup, so the arguments come from scalar loads.
+template <bool BATCH>
+__device__ __forceinline__ void decode_item(const CnnFusedArgs &a0, const CnnFusedArgs *frames,
+                                            const int *tile_off, const int *tile_frame, int item,
+                                            CnnFusedArgs &A, int &tx, int &ty)
+{
+    int local = item;
+    if (BATCH) {
+        const int f = __builtin_amdgcn_readfirstlane(tile_frame[__builtin_amdgcn_readfirstlane(item)]);
+        A = frames[f];
+        local = item - tile_off[f];
+    } else {
+        A = a0;
+    }
+    const int ntx = (A.W + kFT - 1) / kFT;
+    ty = local / ntx;
+    tx = local - ty * ntx;
+}
+
+template <bool BATCH>
 __global__ void __launch_bounds__(kThreads)
-k_cnn_fused(CnnFusedArgs a)
+k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, const int *tile_frame,
+            int n)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned char *bufA = smem + kLdsA;
@@ -257,14 +280,16 @@ k_cnn_fused(CnnFusedArgs a)
     unsigned char *wbuf = smem + kLdsW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int q = lane >> 4, col = lane & 15;
-    const int W = a.W, H = a.H;
-    const int ntx = (W + kFT - 1) / kFT;
-    const int ntiles = ntx * ((H + kFT - 1) / kFT);
+    const int ntiles = BATCH ? tile_off[n]
+                             : ((a.W + kFT - 1) / kFT) * ((a.H + kFT - 1) / kFT);
 
     int tile = blockIdx.x;
     if (tile >= ntiles) return;
+    CnnFusedArgs A;
+    int tx, ty;
+    decode_item<BATCH>(a, frames, tile_off, tile_frame, tile, A, tx, ty);
     FeatRegs f;
-    feat_fetch(a, tile % ntx, tile / ntx, tid, f);
+    feat_fetch(A, tx, ty, tid, f);
     StageRegs r;
     stage_fetch(a, 1, tid, r);
     stage_store(wbuf, 1, tid, r);
@@ -272,7 +297,7 @@ k_cnn_fused(CnnFusedArgs a)
     u32x4 wa[9][2];
     float bs[2][4];
     while (true) {
-        const int tx = tile % ntx, ty = tile / ntx;
+        const int W = A.W, H = A.H;
         const int x0 = tx * kFT, y0 = ty * kFT;
         // ---- features over the 36 x 36 region at (x0-6, y0-6): (x0 bf16, valid bf16)
         uint32_t *feat = reinterpret_cast<uint32_t *>(bufB);
@@ -281,7 +306,7 @@ k_cnn_fused(CnnFusedArgs a)
             const int p = tid + k * kThreads;
             if (p < kRF * kRF) {
                 uint32_t v = 0;
-                if (valid_disp(f.d[k])) v = (uint32_t)bf16_rne((f.d[k] - f.mu[k]) / a.s) | (0x3f80u << 16);
+                if (valid_disp(f.d[k])) v = (uint32_t)bf16_rne((f.d[k] - f.mu[k]) / A.s) | (0x3f80u << 16);
                 feat[p] = v;
             }
         }
@@ -338,7 +363,12 @@ k_cnn_fused(CnnFusedArgs a)
         __syncthreads();
         stage_fetch(a, 6, tid, r);
         const int next = tile + gridDim.x;
-        if (next < ntiles) feat_fetch(a, next % ntx, next / ntx, tid, f);
+        CnnFusedArgs An;
+        int ntx_, nty_;
+        if (next < ntiles) {
+            decode_item<BATCH>(a, frames, tile_off, tile_frame, next, An, ntx_, nty_);
+            feat_fetch(An, ntx_, nty_, tid, f);
+        }
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 6, tid, r);
@@ -378,9 +408,9 @@ k_cnn_fused(CnnFusedArgs a)
                 for (int k = 0; k < 2; ++k) {
                     const int gx = x0 + x[k], gy = y0 + y[k];
                     if (q == 0 && g + kWaves * k < NG && gx < W && gy < H) {
-                        const float mu = a.mu[(int64_t)gy * W + gx];
+                        const float mu = A.mu[(int64_t)gy * W + gx];
                         const float yv = acc[k][0] + b6;
-                        a.out[(int64_t)gy * a.ld_out + gx] = (mu == mu) ? mu + a.s * yv : __builtin_nanf("");
+                        A.out[(int64_t)gy * A.ld_out + gx] = (mu == mu) ? mu + A.s * yv : __builtin_nanf("");
                     }
                 }
             }
@@ -388,20 +418,44 @@ k_cnn_fused(CnnFusedArgs a)
         __syncthreads();
         if (next >= ntiles) break;
         tile = next;
+        A = An;
+        tx = ntx_;
+        ty = nty_;
     }
 }
 
 }  // namespace
 
-hipError_t cnn_forward_fused(const CnnFusedArgs &f, hipStream_t s)
+static int cu_count()
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    const int ntiles = ((f.W + kFT - 1) / kFT) * ((f.H + kFT - 1) / kFT);
+    return cus;
+}
+
+hipError_t cnn_forward_fused(const CnnFusedArgs &f, hipStream_t s)
+{
+    const int ntiles = cnn_fused_tiles(f.W, f.H);
+    const int cus = cu_count();
     const int grid = ntiles < cus ? ntiles : cus;
-    hipLaunchKernelGGL(k_cnn_fused, dim3(grid), dim3(kThreads), kFusedLds, s, f);
+    hipLaunchKernelGGL(k_cnn_fused<false>, dim3(grid), dim3(kThreads), kFusedLds, s, f,
+                       (const CnnFusedArgs *)nullptr, (const int *)nullptr, (const int *)nullptr, 0);
+    return hipGetLastError();
+}
+
+int cnn_fused_tiles(int W, int H) { return ((W + kFT - 1) / kFT) * ((H + kFT - 1) / kFT); }
+
+hipError_t cnn_forward_fused_batch(const CnnFusedArgs &common, const CnnFusedArgs *frames,
+                                   const int *tile_off, const int *tile_frame, int n, int total,
+                                   hipStream_t s)
+{
+    const int cus = cu_count();
+    const int grid = total < cus ? total : cus;
+    if (grid < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_cnn_fused<true>, dim3(grid), dim3(kThreads), kFusedLds, s, common, frames,
+                       tile_off, tile_frame, n);
     return hipGetLastError();
 }
 

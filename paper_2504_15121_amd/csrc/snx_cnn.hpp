@@ -97,6 +97,15 @@ struct CnnFusedArgs {
 
 hipError_t cnn_pack(const float *params, uint16_t *packed, hipStream_t s);
 hipError_t cnn_forward_fused(const CnnFusedArgs &f, hipStream_t s);
+// Number of tiles of the fused kernel for a W x H frame.
+int cnn_fused_tiles(int W, int H);
+// The fused network over the tiles of many frames in one persistent launch:
+// frames = device array of per-frame arguments; item i is tile
+// i - tile_off[f] of frame f = tile_frame[i]; `common` carries the params and
+// packed weights (the same for every frame).
+hipError_t cnn_forward_fused_batch(const CnnFusedArgs &common, const CnnFusedArgs *frames,
+                                   const int *tile_off, const int *tile_frame, int n, int total,
+                                   hipStream_t s);
 hipError_t cnn_forward(const CnnForwardArgs &f, hipStream_t s);
 hipError_t cnn_head(const HeadArgs &h, double *loss_out, hipStream_t s);
 hipError_t cnn_backward(const CnnForwardArgs &f, const float *grad_y, float *partial,

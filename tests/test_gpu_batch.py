@@ -133,13 +133,12 @@ def test_plan_learned_filter_matches_pipeline():
     plan.close()
 
 
-def test_plan_rejects_small_cnn_workspace():
+def test_plan_rejects_incomplete_model():
     snx = _snx()
     from paper_2504_15121_amd import learned
+    from paper_2504_15121_amd._lib import snx_cnn_model
     P = torch.from_numpy(learned.init_params(0)).to(DEV)
-    packed = torch.empty(snx.snx_cnn_packed_bytes() // 2, dtype=torch.int16, device=DEV)
-    snx.snx_cnn_pack(P, packed)
-    ws = torch.empty(snx.snx_cnn_workspace_size(32, 32, 1, 0), dtype=torch.uint8, device=DEV)
     frames = [_alloc(sc) for sc in _frames([(100, 60)], 500)]
-    with pytest.raises(snx.SnxError):
-        snx.Plan(frames, cnn=snx.cnn_model(P, packed, ws))
+    with pytest.raises(snx.SnxError) as ei:
+        snx.Plan(frames, cnn=snx_cnn_model(P.data_ptr(), None, None, 0))   # no packed weights
+    assert ei.value.status == 5
