@@ -34,23 +34,34 @@ __device__ __forceinline__ int gload(const int32_t *p)
 // roots are ever hooked and a non-root never becomes a root again, so the
 // halving cannot undo a concurrent hook; atomicMin keeps every entry
 // monotonically decreasing along its chain of ancestors.
-__device__ __forceinline__ int g_find(int32_t *par, int x)
+// Roots of a and b with both chains advancing together (one round trip per
+// step for the pair instead of one per chain).
+__device__ __forceinline__ void g_find2(int32_t *par, int &a, int &b)
 {
-    while (true) {
-        const int p = gload(par + x);
-        if (p == x) return x;
-        const int gp = gload(par + p);
-        if (gp == p) return p;
-        atomicMin(par + x, gp);
-        x = gp;
+    bool ra = false, rb = false;
+    while (!(ra && rb)) {
+        const int pa = ra ? a : gload(par + a);
+        const int pb = rb ? b : gload(par + b);
+        ra = ra || pa == a;
+        rb = rb || pb == b;
+        if (ra && rb) break;
+        const int ga = ra ? a : gload(par + pa);
+        const int gb = rb ? b : gload(par + pb);
+        if (!ra) {
+            if (ga == pa) { a = pa; ra = true; }
+            else { atomicMin(par + a, ga); a = ga; }
+        }
+        if (!rb) {
+            if (gb == pb) { b = pb; rb = true; }
+            else { atomicMin(par + b, gb); b = gb; }
+        }
     }
 }
 
 __device__ __forceinline__ void g_union(int32_t *par, int a, int b)
 {
     while (true) {
-        a = g_find(par, a);
-        b = g_find(par, b);
+        g_find2(par, a, b);
         if (a == b) return;
         if (a < b) { const int t = a; a = b; b = t; }
         const int old = atomicMin(par + a, b);
