@@ -167,34 +167,51 @@ __device__ __forceinline__ void store_act(unsigned char *out, int p, int q, bool
         make_uint2(w[2], w[3]);
 }
 
+// Strip decomposition of an output region of edge RO >= 17 for the 8 waves: two
+// 16-column segments (at 0 and at RO - 16, overlapping when RO < 32; the
+// overlap is computed twice and written twice with the same values), each
+// split into four runs of consecutive rows.  A wave walks its run downwards,
+// keeping the input rows it still needs in registers, so each output row costs
+// three 16-byte LDS reads per lane (the new input row at dx = -1, 0, +1)
+// instead of nine.
+template <int RO>
+__device__ __forceinline__ void strip_of(int wave, int &xs, int &r0, int &r1)
+{
+    constexpr int rp = (RO + 3) / 4;
+    const int seg = wave >> 2, part = wave & 3;
+    xs = seg == 0 ? 0 : RO - 16;
+    r0 = part * rp;
+    r1 = r0 + rp < RO ? r0 + rp : RO;
+}
+
 // One 32 -> 32 layer from region RIN (`in`) to region RIN - 2 (`out`) with the
 // weights already in registers.  (ox, oy): image coordinates of the output
-// region's first pixel.
+// region's first pixel.  Output rows go two at a time (four accumulator
+// chains); input rows y .. y + 3 are held as F[0..3][dx].
 template <int RIN>
 __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char *out,
                                           const u32x4 (&wa)[9][2], const float (&bs)[2][4],
                                           int ox, int oy, int W, int H, int lane, int wave)
 {
     constexpr int RO = RIN - 2;
-    constexpr int NP = RO * RO;
-    constexpr int NG = (NP + 15) / 16;
     const int q = lane >> 4, col = lane & 15;
-    // two groups (g, g + kWaves) per iteration: four independent accumulator chains
-    for (int g = wave; g < NG; g += 2 * kWaves) {
-        int p[2], x[2], y[2], base[2];
+    int xs, r0, r1;
+    strip_of<RO>(wave, xs, r0, r1);
+    const int xin = xs + col;                 // input column of tap dx = -1
+    u32x4 F[4][3];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            p[k] = (g + kWaves * k) * 16 + col;
-            const int pc = p[k] < NP ? p[k] : NP - 1;
-            y[k] = pc / RO;
-            x[k] = pc - y[k] * RO;
-            base[k] = (y[k] + 1) * RIN + x[k] + 1;
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) F[k][d] = lds16(in, (r0 + k) * RIN + xin + d, q);
+#pragma unroll 1
+    for (int y = r0; y < r1; y += 2) {
+        const bool two = y + 1 < r1;
+        const int y3 = two ? y + 3 : y + 2;   // a lone last row reads row y + 2 twice
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            F[2][d] = lds16(in, (y + 2) * RIN + xin + d, q);
+            F[3][d] = lds16(in, y3 * RIN + xin + d, q);
         }
-        u32x4 bv[2][9];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int t = 0; t < 9; ++t) bv[k][t] = lds16(in, base[k] + (t / 3 - 1) * RIN + (t % 3 - 1), q);
         f32x4 acc[2][2];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
@@ -205,14 +222,19 @@ __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int k = 0; k < 2; ++k) acc[k][mb] = mfma(wa[t][mb], bv[k][t], acc[k][mb]);
+                for (int k = 0; k < 2; ++k) acc[k][mb] = mfma(wa[t][mb], F[k + t / 3][t % 3], acc[k][mb]);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            if (p[k] < NP) {
-                const int gx = ox + x[k], gy = oy + y[k];
+            if (k == 0 || two) {
+                const int gx = ox + xs + col, gy = oy + y + k;
                 const bool inside = gx >= 0 && gx < W && gy >= 0 && gy < H;
-                store_act(out, p[k], q, inside, acc[k][0], acc[k][1], bs);
+                store_act(out, (y + k) * RO + xs + col, q, inside, acc[k][0], acc[k][1], bs);
             }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            F[0][d] = F[2][d];
+            F[1][d] = F[3][d];
         }
     }
 }
@@ -278,8 +300,7 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
     unsigned char *bufA = smem + kLdsA;
     unsigned char *bufB = smem + kLdsB;
     unsigned char *wbuf = smem + kLdsW;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q = lane >> 4, col = lane & 15;
+    const int tid = threadIdx.x, lane0 = tid & 63, wave0 = tid >> 6;
     const int ntiles = BATCH ? tile_off[n]
                              : ((a.W + kFT - 1) / kFT) * ((a.H + kFT - 1) / kFT);
 
@@ -297,6 +318,12 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
     u32x4 wa[9][2];
     float bs[2][4];
     while (true) {
+        // Lane and wave indices redefined per tile: this keeps the compiler from
+        // hoisting every layer's strip addresses out of the tile loop, which
+        // would hold them in (spilled) registers for the whole kernel.
+        int lane = lane0, wave = wave0;
+        asm volatile("" : "+v"(lane), "+v"(wave));
+        const int q = lane >> 4, col = lane & 15;
         const int W = A.W, H = A.H;
         const int x0 = tx * kFT, y0 = ty * kFT;
         // ---- features over the 36 x 36 region at (x0-6, y0-6): (x0 bf16, valid bf16)
@@ -376,42 +403,51 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
         __syncthreads();
         stage_fetch(a, 1, tid, r);
 
-        // ---- layer 6: 32 -> 1 on the 24 x 24 tile, 16 consecutive pixels per group
+        // ---- layer 6: 32 -> 1 on the 24 x 24 tile, strips as in the middle layers
         {
-            constexpr int RIN = kFT + 2, NP = kFT * kFT, NG = NP / 16;
+            constexpr int RIN = kFT + 2, RO = kFT;
             u32x4 w6[9];
 #pragma unroll
             for (int t = 0; t < 9; ++t) w6[t] = lds16(wbuf, t * 16 + col, q);
             const float b6 = reinterpret_cast<const float *>(wbuf + kWBias)[0];
             __syncthreads();                              // every wave holds layer 6's weights
             stage_store(wbuf, 1, tid, r);
-            for (int g = wave; g < NG; g += 2 * kWaves) {
-                int p[2], x[2], y[2];
-                u32x4 bv[2][9];
+            int xs, r0, r1;
+            strip_of<RO>(wave, xs, r0, r1);
+            const int xin = xs + col;
+            u32x4 F[4][3];
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int gg = g + kWaves * k;
-                    p[k] = (gg < NG ? gg : NG - 1) * 16 + col;
-                    y[k] = p[k] / kFT;
-                    x[k] = p[k] - y[k] * kFT;
-                    const int base = (y[k] + 1) * RIN + x[k] + 1;
+            for (int k = 0; k < 2; ++k)
 #pragma unroll
-                    for (int t = 0; t < 9; ++t) bv[k][t] = lds16(bufA, base + (t / 3 - 1) * RIN + (t % 3 - 1), q);
+                for (int d = 0; d < 3; ++d) F[k][d] = lds16(bufA, (r0 + k) * RIN + xin + d, q);
+#pragma unroll 1
+            for (int y = r0; y < r1; y += 2) {
+                const bool two = y + 1 < r1;
+                const int y3 = two ? y + 3 : y + 2;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    F[2][d] = lds16(bufA, (y + 2) * RIN + xin + d, q);
+                    F[3][d] = lds16(bufA, y3 * RIN + xin + d, q);
                 }
                 f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
                 for (int t = 0; t < 9; ++t)
 #pragma unroll
-                    for (int k = 0; k < 2; ++k) acc[k] = mfma(w6[t], bv[k][t], acc[k]);
+                    for (int k = 0; k < 2; ++k) acc[k] = mfma(w6[t], F[k + t / 3][t % 3], acc[k]);
                 // output channel 0 of each pixel sits in lanes q == 0, element 0
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const int gx = x0 + x[k], gy = y0 + y[k];
-                    if (q == 0 && g + kWaves * k < NG && gx < W && gy < H) {
+                    const int gx = x0 + xs + col, gy = y0 + y + k;
+                    if (q == 0 && (k == 0 || two) && gx < W && gy < H) {
                         const float mu = A.mu[(int64_t)gy * W + gx];
                         const float yv = acc[k][0] + b6;
                         A.out[(int64_t)gy * A.ld_out + gx] = (mu == mu) ? mu + A.s * yv : __builtin_nanf("");
                     }
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    F[0][d] = F[2][d];
+                    F[1][d] = F[3][d];
                 }
             }
         }
