@@ -54,7 +54,8 @@ constexpr int kWBuf = kWBias + 32 * 4;                  // 18560
 constexpr int kLdsA = 0;
 constexpr int kLdsB = kLdsA + kRA * kRA * 64;           // 73984
 constexpr int kLdsW = kLdsB + kRB * kRB * 64;           // 139520
-constexpr size_t kFusedLds = kLdsW + kWBuf;             // 158080 bytes
+constexpr int kLdsMu = kLdsW + kWBuf;                   // mu of the output tile (float)
+constexpr size_t kFusedLds = kLdsMu + kFT * kFT * 4;    // 160384 bytes
 
 // feature pixels per thread (36 x 36 region over 512 threads)
 constexpr int kFeatPer = (kRF * kRF + kThreads - 1) / kThreads;   // 3
@@ -79,13 +80,20 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c)
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// byte offset of 16-byte chunk c of pixel (or weight row) p
+// Byte offset of 16-byte chunk c of weight row p.
 __device__ __forceinline__ int chunk_off(int p, int c) { return p * 64 + ((c ^ ((p >> 1) & 3)) << 4); }
 
 __device__ __forceinline__ u32x4 lds16(const unsigned char *base, int p, int c)
 {
     return *reinterpret_cast<const u32x4 *>(base + chunk_off(p, c));
 }
+
+// Activations swizzle by the pixel's column x instead: chunk c of a pixel in
+// column x sits at slot c ^ ((x >> 1) & 3).  Any 8 horizontally consecutive
+// pixels then cover the 8 bank groups whatever the row pitch, and a lane that
+// walks down a column keeps one swizzle, so its addresses differ by whole rows
+// (immediate offsets).
+__device__ __forceinline__ int act_slot(int x, int c) { return (c ^ ((x >> 1) & 3)) << 4; }
 
 // ---------------------------------------------------------------------------
 // Weight staging.  Stage s = 1..6 is layer s.  Its packed weights are
@@ -142,10 +150,18 @@ __device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, floa
 
 // ---------------------------------------------------------------------------
 // Bias, ReLU, zero outside the image, bf16, and store of one lane's results:
-// output channels 4q..4q+3 (block 0) and 16+4q..16+4q+3 (block 1) of pixel p.
-// bl[mb][j] = bias of output channel mb * 16 + 4q + j.
+// output channels 4q..4q+3 (block 0) and 16+4q..16+4q+3 (block 1) of a pixel.
+// px: the pixel's 64 bytes; o0 / o1: byte offsets of the two 8-byte halves
+// (act_offsets).  bl[mb][j] = bias of output channel mb * 16 + 4q + j.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void store_act(unsigned char *out, int p, int q, bool inside,
+__device__ __forceinline__ void act_offsets(int x, int q, int &o0, int &o1)
+{
+    // channels 4q.. sit in chunk q/2 (half q&1); channels 16+4q.. in chunk 2 + q/2
+    o0 = act_slot(x, q >> 1) + ((q & 1) << 3);
+    o1 = act_slot(x, 2 + (q >> 1)) + ((q & 1) << 3);
+}
+
+__device__ __forceinline__ void store_act(unsigned char *px, int o0, int o1, bool inside,
                                           const f32x4 &a0, const f32x4 &a1, const float (&bl)[2][4])
 {
     uint32_t w[4];
@@ -161,81 +177,102 @@ __device__ __forceinline__ void store_act(unsigned char *out, int p, int q, bool
         w[2 * mb] = inside ? pack_bf16(v[0], v[1]) : 0u;
         w[2 * mb + 1] = inside ? pack_bf16(v[2], v[3]) : 0u;
     }
-    // channels 4q.. sit in chunk q/2 (half q&1); channels 16+4q.. in chunk 2 + q/2
-    *reinterpret_cast<uint2 *>(out + chunk_off(p, q >> 1) + ((q & 1) << 3)) = make_uint2(w[0], w[1]);
-    *reinterpret_cast<uint2 *>(out + chunk_off(p, 2 + (q >> 1)) + ((q & 1) << 3)) =
-        make_uint2(w[2], w[3]);
+    *reinterpret_cast<uint2 *>(px + o0) = make_uint2(w[0], w[1]);
+    *reinterpret_cast<uint2 *>(px + o1) = make_uint2(w[2], w[3]);
 }
 
-// Strip decomposition of an output region of edge RO >= 17 for the 8 waves: two
-// 16-column segments (at 0 and at RO - 16, overlapping when RO < 32; the
-// overlap is computed twice and written twice with the same values), each
-// split into four runs of consecutive rows.  A wave walks its run downwards,
-// keeping the input rows it still needs in registers, so each output row costs
-// three 16-byte LDS reads per lane (the new input row at dx = -1, 0, +1)
-// instead of nine.
+// Strip decomposition of an output region of even edge RO in [16, 32] for the
+// 8 waves: two 16-column segments (at 0 and at RO - 16, overlapping when
+// RO < 32; the overlap is computed twice and written twice with the same
+// values), each split into four runs of consecutive row pairs.  A wave walks
+// its run downwards, keeping the input rows it still needs in registers, so
+// each output row costs three 16-byte LDS reads per lane (the new input row at
+// dx = -1, 0, +1) instead of nine.  Waves w and w + 4 share a SIMD; the second
+// segment takes its runs in reverse order so that a long run and a short run
+// share a SIMD whenever the pairs do not divide evenly.
 template <int RO>
 __device__ __forceinline__ void strip_of(int wave, int &xs, int &r0, int &r1)
 {
-    constexpr int rp = (RO + 3) / 4;
-    const int seg = wave >> 2, part = wave & 3;
+    static_assert(RO % 2 == 0 && RO >= 16 && RO <= 32, "strip layout");
+    constexpr int kPairs = RO / 2, kBase = kPairs / 4, kExtra = kPairs % 4;
+    const int seg = wave >> 2;
+    const int part = seg == 0 ? (wave & 3) : 3 - (wave & 3);
+    const int p0 = part * kBase + (part < kExtra ? part : kExtra);
+    const int np = kBase + (part < kExtra ? 1 : 0);
     xs = seg == 0 ? 0 : RO - 16;
-    r0 = part * rp;
-    r1 = r0 + rp < RO ? r0 + rp : RO;
+    r0 = 2 * p0;
+    r1 = 2 * (p0 + np);
 }
 
 // One 32 -> 32 layer from region RIN (`in`) to region RIN - 2 (`out`) with the
 // weights already in registers.  (ox, oy): image coordinates of the output
-// region's first pixel.  Output rows go two at a time (four accumulator
-// chains); input rows y .. y + 3 are held as F[0..3][dx].
+// region's first pixel.  A step computes two output rows (four accumulator
+// chains) from input rows 2s .. 2s + 3 of the wave's run (F[row][dx]); the
+// steps are unrolled and software-pipelined: step s's MFMAs are issued in the
+// same block as step s - 1's bias, ReLU, packing and stores, so the matrix
+// core and the vector ALU of a wave work at the same time.
 template <int RIN>
 __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char *out,
                                           const u32x4 (&wa)[9][2], const float (&bs)[2][4],
                                           int ox, int oy, int W, int H, int lane, int wave)
 {
-    constexpr int RO = RIN - 2;
+    constexpr int RO = RIN - 2, kSteps = (RO / 2 + 3) / 4;
     const int q = lane >> 4, col = lane & 15;
     int xs, r0, r1;
     strip_of<RO>(wave, xs, r0, r1);
-    const int xin = xs + col;                 // input column of tap dx = -1
-    u32x4 F[4][3];
+    const bool full = r1 - r0 == 2 * kSteps;      // else the run has kSteps - 1 steps
+    const int x = xs + col;                        // output column; input columns x .. x + 2
+    const unsigned char *src[3];
 #pragma unroll
-    for (int k = 0; k < 2; ++k)
+    for (int d = 0; d < 3; ++d) src[d] = in + (r0 * RIN + x + d) * 64 + act_slot(x + d, q);
+    unsigned char *dst = out + (r0 * RO + x) * 64;
+    int o0, o1;
+    act_offsets(x, q, o0, o1);
+    const int gx = ox + x, gy0 = oy + r0;
+    const bool col_in = gx >= 0 && gx < W;
+
+    u32x4 F[2 * kSteps + 2][3];
+    f32x4 acc[kSteps][2][2];
+    auto load_row = [&](int j) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) F[k][d] = lds16(in, (r0 + k) * RIN + xin + d, q);
-#pragma unroll 1
-    for (int y = r0; y < r1; y += 2) {
-        const bool two = y + 1 < r1;
-        const int y3 = two ? y + 3 : y + 2;   // a lone last row reads row y + 2 twice
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            F[2][d] = lds16(in, (y + 2) * RIN + xin + d, q);
-            F[3][d] = lds16(in, y3 * RIN + xin + d, q);
-        }
-        f32x4 acc[2][2];
+        for (int d = 0; d < 3; ++d) F[j][d] = *reinterpret_cast<const u32x4 *>(src[d] + j * RIN * 64);
+    };
+    auto compute = [&](int st) {
+        load_row(2 * st + 2);
+        load_row(2 * st + 3);
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) acc[k][mb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int mb = 0; mb < 2; ++mb) acc[st][k][mb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; ++t)
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-                for (int k = 0; k < 2; ++k) acc[k][mb] = mfma(wa[t][mb], F[k + t / 3][t % 3], acc[k][mb]);
+                for (int k = 0; k < 2; ++k)
+                    acc[st][k][mb] = mfma(wa[t][mb], F[2 * st + k + t / 3][t % 3], acc[st][k][mb]);
+    };
+    auto finish = [&](int st) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            if (k == 0 || two) {
-                const int gx = ox + xs + col, gy = oy + y + k;
-                const bool inside = gx >= 0 && gx < W && gy >= 0 && gy < H;
-                store_act(out, (y + k) * RO + xs + col, q, inside, acc[k][0], acc[k][1], bs);
-            }
+            const bool inside = col_in && (unsigned)(gy0 + 2 * st + k) < (unsigned)H;
+            store_act(dst + (2 * st + k) * RO * 64, o0, o1, inside, acc[st][k][0], acc[st][k][1], bs);
         }
+    };
+    load_row(0);
+    load_row(1);
+    compute(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            F[0][d] = F[2][d];
-            F[1][d] = F[3][d];
-        }
+    for (int st = 1; st < kSteps - 1; ++st) {
+        compute(st);
+        finish(st - 1);
+    }
+    if (full) {
+        compute(kSteps - 1);
+        finish(kSteps - 2);
+        finish(kSteps - 1);
+    } else {
+        finish(kSteps - 2);
     }
 }
 
@@ -311,9 +348,12 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
     decode_item<BATCH>(a, frames, tile_off, tile_frame, tile, A, tx, ty);
     FeatRegs f;
     feat_fetch(A, tx, ty, tid, f);
+    // Weight stages: the stage stored at a layer's start is fetched into
+    // registers one layer earlier, at the previous layer's start.
     StageRegs r;
     stage_fetch(a, 1, tid, r);
     stage_store(wbuf, 1, tid, r);
+    stage_fetch(a, 2, tid, r);
 
     u32x4 wa[9][2];
     float bs[2][4];
@@ -326,8 +366,10 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
         const int q = lane >> 4, col = lane & 15;
         const int W = A.W, H = A.H;
         const int x0 = tx * kFT, y0 = ty * kFT;
-        // ---- features over the 36 x 36 region at (x0-6, y0-6): (x0 bf16, valid bf16)
+        // ---- features over the 36 x 36 region at (x0-6, y0-6): (x0 bf16, valid bf16);
+        // mu of the 24 x 24 output pixels goes to its own LDS array for layer 6
         uint32_t *feat = reinterpret_cast<uint32_t *>(bufB);
+        float *s_mu = reinterpret_cast<float *>(smem + kLdsMu);
 #pragma unroll
         for (int k = 0; k < kFeatPer; ++k) {
             const int p = tid + k * kThreads;
@@ -335,9 +377,10 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
                 uint32_t v = 0;
                 if (valid_disp(f.d[k])) v = (uint32_t)bf16_rne((f.d[k] - f.mu[k]) / A.s) | (0x3f80u << 16);
                 feat[p] = v;
+                const int ly = p / kRF - 6, lx = p % kRF - 6;
+                if ((unsigned)ly < (unsigned)kFT && (unsigned)lx < (unsigned)kFT) s_mu[ly * kFT + lx] = f.mu[k];
             }
         }
-        stage_fetch(a, 2, tid, r);
         __syncthreads();                                  // features and layer-1 weights ready
 
         // ---- layer 1: 2 -> 32, K slots = tap * 2 + channel (18 used)
@@ -348,47 +391,66 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             load_bias(wbuf, q, bs);
             __syncthreads();                              // every wave holds layer 1's weights
             stage_store(wbuf, 2, tid, r);
+            stage_fetch(a, 3, tid, r);
+            // groups of 16 consecutive region pixels, group g to wave g % 8, taken
+            // kL1Batch at a time so that their feature reads are in flight together
             constexpr int RO = kRA, NP = RO * RO, NG = (NP + 15) / 16;
-            for (int g = wave; g < NG; g += kWaves) {
-                const int p = g * 16 + col;
-                const int pc = p < NP ? p : NP - 1;
-                const int y = pc / RO, x = pc - y * RO;
-                u32x4 bv;
+            constexpr int kL1Batch = 5, kL1Iter = (NG + kWaves - 1) / kWaves;
+            static_assert(kL1Iter % kL1Batch == 0, "layer-1 batching");
+#pragma unroll 1
+            for (int j0 = 0; j0 < kL1Iter; j0 += kL1Batch) {
+                u32x4 bv[kL1Batch];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int t = 4 * q + i;                    // this lane's slots 8q .. 8q+7
-                    uint32_t v = 0;
-                    if (t < 9) v = feat[(y + t / 3) * kRF + x + t % 3];
-                    bv[i] = v;
+                for (int b = 0; b < kL1Batch; ++b) {
+                    const int p = (wave + kWaves * (j0 + b)) * 16 + col;
+                    const int pc = p < NP ? p : NP - 1;
+                    const int y = pc / RO, x = pc - y * RO;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int t = 4 * q + i;                // this lane's slots 8q .. 8q+7
+                        uint32_t v = 0;
+                        if (t < 9) v = feat[(y + t / 3) * kRF + x + t % 3];
+                        bv[b][i] = v;
+                    }
                 }
-                const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                const f32x4 a0 = mfma(w1[0], bv, z), a1 = mfma(w1[1], bv, z);
-                if (p < NP) {
-                    const int gx = x0 - 5 + x, gy = y0 - 5 + y;
-                    store_act(bufA, p, q, gx >= 0 && gx < W && gy >= 0 && gy < H, a0, a1, bs);
+#pragma unroll
+                for (int b = 0; b < kL1Batch; ++b) {
+                    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                    const f32x4 a0 = mfma(w1[0], bv[b], z), a1 = mfma(w1[1], bv[b], z);
+                    const int p = (wave + kWaves * (j0 + b)) * 16 + col;
+                    if (p < NP) {
+                        const int y = p / RO, x = p - y * RO;
+                        const int gx = x0 - 5 + x, gy = y0 - 5 + y;
+                        int o0, o1;
+                        act_offsets(x, q, o0, o1);
+                        store_act(bufA + p * 64, o0, o1, gx >= 0 && gx < W && gy >= 0 && gy < H, a0, a1, bs);
+                    }
                 }
             }
         }
         __syncthreads();                                  // layer 1 out and layer-2 weights ready
-        stage_fetch(a, 3, tid, r);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 3, tid, r);
+        stage_fetch(a, 4, tid, r);
         mid_layer<kRA>(bufA, bufB, wa, bs, x0 - 4, y0 - 4, W, H, lane, wave);
         __syncthreads();
-        stage_fetch(a, 4, tid, r);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 4, tid, r);
+        stage_fetch(a, 5, tid, r);
         mid_layer<kRB>(bufB, bufA, wa, bs, x0 - 3, y0 - 3, W, H, lane, wave);
         __syncthreads();
-        stage_fetch(a, 5, tid, r);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 5, tid, r);
+        stage_fetch(a, 6, tid, r);
         mid_layer<kRB - 2>(bufA, bufB, wa, bs, x0 - 2, y0 - 2, W, H, lane, wave);
         __syncthreads();
-        stage_fetch(a, 6, tid, r);
+        load_mid_weights(wbuf, q, col, wa, bs);
+        __syncthreads();
+        stage_store(wbuf, 6, tid, r);
+        stage_fetch(a, 1, tid, r);
         const int next = tile + gridDim.x;
         CnnFusedArgs An;
         int ntx_, nty_;
@@ -396,12 +458,8 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             decode_item<BATCH>(a, frames, tile_off, tile_frame, next, An, ntx_, nty_);
             feat_fetch(An, ntx_, nty_, tid, f);
         }
-        load_mid_weights(wbuf, q, col, wa, bs);
-        __syncthreads();
-        stage_store(wbuf, 6, tid, r);
         mid_layer<kRB - 4>(bufB, bufA, wa, bs, x0 - 1, y0 - 1, W, H, lane, wave);
         __syncthreads();
-        stage_fetch(a, 1, tid, r);
 
         // ---- layer 6: 32 -> 1 on the 24 x 24 tile, strips as in the middle layers
         {
@@ -412,44 +470,52 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             const float b6 = reinterpret_cast<const float *>(wbuf + kWBias)[0];
             __syncthreads();                              // every wave holds layer 6's weights
             stage_store(wbuf, 1, tid, r);
+            stage_fetch(a, 2, tid, r);
+            // three steps of two rows for every wave, pipelined as in mid_layer
+            static_assert(RO / 2 == 4 * 3, "layer-6 strip runs");
             int xs, r0, r1;
             strip_of<RO>(wave, xs, r0, r1);
-            const int xin = xs + col;
-            u32x4 F[4][3];
+            const int x = xs + col;
+            const unsigned char *src[3];
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int d = 0; d < 3; ++d) src[d] = bufA + (r0 * RIN + x + d) * 64 + act_slot(x + d, q);
+            const int gx = x0 + x;
+            const bool col_in = q == 0 && gx < W;       // output channel 0: lanes q == 0, element 0
+            u32x4 F[8][3];
+            f32x4 acc[3][2];
+            auto load_row = [&](int j) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) F[k][d] = lds16(bufA, (r0 + k) * RIN + xin + d, q);
-#pragma unroll 1
-            for (int y = r0; y < r1; y += 2) {
-                const bool two = y + 1 < r1;
-                const int y3 = two ? y + 3 : y + 2;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    F[2][d] = lds16(bufA, (y + 2) * RIN + xin + d, q);
-                    F[3][d] = lds16(bufA, y3 * RIN + xin + d, q);
-                }
-                f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                for (int d = 0; d < 3; ++d) F[j][d] = *reinterpret_cast<const u32x4 *>(src[d] + j * RIN * 64);
+            };
+            auto compute = [&](int st) {
+                load_row(2 * st + 2);
+                load_row(2 * st + 3);
+                acc[st][0] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                acc[st][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int t = 0; t < 9; ++t)
 #pragma unroll
-                    for (int k = 0; k < 2; ++k) acc[k] = mfma(w6[t], F[k + t / 3][t % 3], acc[k]);
-                // output channel 0 of each pixel sits in lanes q == 0, element 0
+                    for (int k = 0; k < 2; ++k) acc[st][k] = mfma(w6[t], F[2 * st + k + t / 3][t % 3], acc[st][k]);
+            };
+            auto finish = [&](int st) {
 #pragma unroll
                 for (int k = 0; k < 2; ++k) {
-                    const int gx = x0 + xs + col, gy = y0 + y + k;
-                    if (q == 0 && (k == 0 || two) && gx < W && gy < H) {
-                        const float mu = A.mu[(int64_t)gy * W + gx];
-                        const float yv = acc[k][0] + b6;
+                    const int ly = r0 + 2 * st + k, gy = y0 + ly;
+                    if (col_in && gy < H) {
+                        const float mu = s_mu[ly * kFT + x];
+                        const float yv = acc[st][k][0] + b6;
                         A.out[(int64_t)gy * A.ld_out + gx] = (mu == mu) ? mu + A.s * yv : __builtin_nanf("");
                     }
                 }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    F[0][d] = F[2][d];
-                    F[1][d] = F[3][d];
-                }
-            }
+            };
+            load_row(0);
+            load_row(1);
+            compute(0);
+            compute(1);
+            finish(0);
+            compute(2);
+            finish(1);
+            finish(2);
         }
         __syncthreads();
         if (next >= ntiles) break;
