@@ -52,9 +52,10 @@ __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
 
 // ----------------------------------------------------------------------------
 // Middle-layer convolution (32 -> 32 channels, or 32 -> 1 when LAST).
-//   MODE 0: forward, bias + ReLU, bf16 NHWC out
+//   MODE 0: forward, bias (the accumulators' initial value) + ReLU, bf16 NHWC out
 //   MODE 1: backward-data, multiply by [mask_src > 0], bf16 NHWC out
-//   MODE 2: last layer forward: D~ = mu + s * (y + b) at valid pixels (f32 out)
+//   MODE 2: last layer forward: D~ = mu + s * y at valid pixels, y starting from
+//           the bias (f32 out)
 // wts: [9 taps][N][32] bf16 (N = 32, or 16 with only row 0 used for MODE 2).
 // ----------------------------------------------------------------------------
 template <int MODE>
@@ -93,11 +94,14 @@ k_conv32(ConvArgs a)
     }
     __syncthreads();
 
+    // the bias is the accumulators' initial value (lane: output channel nb*16 + l%16)
     f32x4 acc[4][NB];
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int nb = 0; nb < NB; ++nb) {
+        const float b0 = MODE == 0 ? a.bias[nb * 16 + (lane & 15)] : MODE == 2 ? a.bias[0] : 0.0f;
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int mb = 0; mb < 4; ++mb) acc[mb][nb] = (f32x4){b0, b0, b0, b0};
+    }
     {
         const int col = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -127,7 +131,7 @@ k_conv32(ConvArgs a)
                     if (gx < W && gy < H) {
                         const int64_t o = (int64_t)b * plane + (int64_t)gy * W + gx;
                         const float mu = a.mu[o];
-                        const float y = acc[mb][0][j] + a.bias[0];
+                        const float y = acc[mb][0][j];
                         a.out[(int64_t)b * a.crop_stride_out + (int64_t)gy * a.ld_out + gx] =
                             (mu == mu) ? mu + a.s * y : __builtin_nanf("");
                     }
@@ -147,11 +151,10 @@ k_conv32(ConvArgs a)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int ch = nb * 16 + n;
-                const float bias = MODE == 0 ? a.bias[ch] : 0.0f;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int p = row * kT + 4 * g + j;
-                    float v = acc[mb][nb][j] + bias;
+                    float v = acc[mb][nb][j];
                     if (MODE == 0) v = v > 0.0f ? v : 0.0f;
                     tile[p * 32 + ch] = to_bf16(v);
                 }
@@ -230,6 +233,13 @@ k_conv_small(ConvArgs a)
 
     f32x4 acc[4][2];
     const int col = lane & 15, g = lane >> 4;
+    // first layer: the bias is the accumulators' initial value
+    f32x4 bias0[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const float b0 = C_IN == 2 ? a.bias[nb * 16 + col] : 0.0f;
+        bias0[nb] = (f32x4){b0, b0, b0, b0};
+    }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
         const int row = wave * 4 + mb;
@@ -251,7 +261,7 @@ k_conv_small(ConvArgs a)
         for (int i = 0; i < 4; ++i) ap[i] = (uint32_t)av[2 * i] | ((uint32_t)av[2 * i + 1] << 16);
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb)
-            acc[mb][nb] = mfma(as_bf16x8(ap), as_bf16x8(wb[nb]), (f32x4){0.f, 0.f, 0.f, 0.f});
+            acc[mb][nb] = mfma(as_bf16x8(ap), as_bf16x8(wb[nb]), bias0[nb]);
     }
     const int n = lane & 15;
 #pragma unroll
@@ -260,10 +270,9 @@ k_conv_small(ConvArgs a)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
             const int ch = nb * 16 + n;
-            const float bias = C_IN == 2 ? a.bias[ch] : 0.0f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                float v = acc[mb][nb][j] + bias;
+                float v = acc[mb][nb][j];
                 if (C_IN == 2) v = v > 0.0f ? v : 0.0f;
                 tile[(row * kT + 4 * g + j) * 32 + ch] = to_bf16(v);
             }

@@ -24,8 +24,9 @@
 // 8 lanes served together by a 16-byte LDS read (8 consecutive pixels, one
 // chunk) hit 8 distinct bank groups; weight rows are swizzled the same way.
 //
-// The arithmetic per output is that of the layer-by-layer kernels (same taps in
-// the same order, same MFMA, bias added to the FP32 sum, ReLU, bf16 RNE).
+// Per output: the same MFMA over the taps in the same order as the
+// layer-by-layer kernels, with the bias as the accumulator's initial value
+// (they add it to the finished FP32 sum), then ReLU and bf16 RNE.
 #include <stdint.h>
 
 #include "snx_cnn.hpp"
@@ -38,6 +39,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kFT = 24;                 // output tile edge
 constexpr int kRA = kFT + 10;           // largest region held in buffer A (layer 1 output)
@@ -139,7 +141,9 @@ __device__ __forceinline__ void stage_store(unsigned char *wbuf, int s, int tid,
         *reinterpret_cast<u32x4 *>(wbuf + kWBias + tid * 16) = r.bias;
 }
 
-__device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, float (&bl)[2][4])
+// bl[mb][j] = bias of output channel mb * 16 + 4q + j: the accumulator's initial
+// value in the MFMA layout.
+__device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, f32x4 (&bl)[2])
 {
     const float *b = reinterpret_cast<const float *>(wbuf + kWBias);
 #pragma unroll
@@ -149,10 +153,12 @@ __device__ __forceinline__ void load_bias(const unsigned char *wbuf, int q, floa
 }
 
 // ---------------------------------------------------------------------------
-// Bias, ReLU, zero outside the image, bf16, and store of one lane's results:
-// output channels 4q..4q+3 (block 0) and 16+4q..16+4q+3 (block 1) of a pixel.
-// px: the pixel's 64 bytes; o0 / o1: byte offsets of the two 8-byte halves
-// (act_offsets).  bl[mb][j] = bias of output channel mb * 16 + 4q + j.
+// bf16, ReLU, zero outside the image, and store of one lane's results (bias
+// already in the sums): output channels 4q..4q+3 (block 0) and 16+4q..16+4q+3
+// (block 1) of a pixel.  px: the pixel's 64 bytes; o0 / o1: byte offsets of the
+// two 8-byte halves (act_offsets).  ReLU is a signed 16-bit max with 0 on the
+// packed bf16 pair: rounding to bf16 keeps the sign, so this equals rounding
+// the ReLU of the FP32 value.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void act_offsets(int x, int q, int &o0, int &o1)
 {
@@ -161,21 +167,21 @@ __device__ __forceinline__ void act_offsets(int x, int q, int &o0, int &o1)
     o1 = act_slot(x, 2 + (q >> 1)) + ((q & 1) << 3);
 }
 
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w)
+{
+    const s16x2 v = __builtin_bit_cast(s16x2, w);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, (s16x2){0, 0}));
+}
+
 __device__ __forceinline__ void store_act(unsigned char *px, int o0, int o1, bool inside,
-                                          const f32x4 &a0, const f32x4 &a1, const float (&bl)[2][4])
+                                          const f32x4 &a0, const f32x4 &a1)
 {
     uint32_t w[4];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
         const f32x4 &a = mb ? a1 : a0;
-        float v[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = a[j] + bl[mb][j];
-            v[j] = v[j] > 0.0f ? v[j] : 0.0f;
-        }
-        w[2 * mb] = inside ? pack_bf16(v[0], v[1]) : 0u;
-        w[2 * mb + 1] = inside ? pack_bf16(v[2], v[3]) : 0u;
+        w[2 * mb] = inside ? relu_bf16x2(pack_bf16(a[0], a[1])) : 0u;
+        w[2 * mb + 1] = inside ? relu_bf16x2(pack_bf16(a[2], a[3])) : 0u;
     }
     *reinterpret_cast<uint2 *>(px + o0) = make_uint2(w[0], w[1]);
     *reinterpret_cast<uint2 *>(px + o1) = make_uint2(w[2], w[3]);
@@ -213,7 +219,7 @@ __device__ __forceinline__ void strip_of(int wave, int &xs, int &r0, int &r1)
 // core and the vector ALU of a wave work at the same time.
 template <int RIN>
 __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char *out,
-                                          const u32x4 (&wa)[9][2], const float (&bs)[2][4],
+                                          const u32x4 (&wa)[9][2], const f32x4 (&bs)[2],
                                           int ox, int oy, int W, int H, int lane, int wave)
 {
     constexpr int RO = RIN - 2, kSteps = (RO / 2 + 3) / 4;
@@ -243,7 +249,7 @@ __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) acc[st][k][mb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int mb = 0; mb < 2; ++mb) acc[st][k][mb] = bs[mb];
 #pragma unroll
         for (int t = 0; t < 9; ++t)
 #pragma unroll
@@ -256,7 +262,7 @@ __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const bool inside = col_in && (unsigned)(gy0 + 2 * st + k) < (unsigned)H;
-            store_act(dst + (2 * st + k) * RO * 64, o0, o1, inside, acc[st][k][0], acc[st][k][1], bs);
+            store_act(dst + (2 * st + k) * RO * 64, o0, o1, inside, acc[st][k][0], acc[st][k][1]);
         }
     };
     load_row(0);
@@ -277,7 +283,7 @@ __device__ __forceinline__ void mid_layer(const unsigned char *in, unsigned char
 }
 
 __device__ __forceinline__ void load_mid_weights(const unsigned char *wbuf, int q, int col,
-                                                 u32x4 (&wa)[9][2], float (&bs)[2][4])
+                                                 u32x4 (&wa)[9][2], f32x4 (&bs)[2])
 {
 #pragma unroll
     for (int t = 0; t < 9; ++t)
@@ -356,7 +362,7 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
     stage_fetch(a, 2, tid, r);
 
     u32x4 wa[9][2];
-    float bs[2][4];
+    f32x4 bs[2];
     while (true) {
         // Lane and wave indices redefined per tile: this keeps the compiler from
         // hoisting every layer's strip addresses out of the tile loop, which
@@ -397,6 +403,16 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             constexpr int RO = kRA, NP = RO * RO, NG = (NP + 15) / 16;
             constexpr int kL1Batch = 5, kL1Iter = (NG + kWaves - 1) / kWaves;
             static_assert(kL1Iter % kL1Batch == 0, "layer-1 batching");
+            // this lane's K slots 8q .. 8q+7 are taps 4q .. 4q+3 (x0, valid pairs);
+            // slots past tap 8 read the pixel's own tap 0 and are zeroed
+            int toff[4];
+            bool tuse[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * q + i;
+                tuse[i] = t < 9;
+                toff[i] = tuse[i] ? (t / 3) * kRF + t % 3 : 0;
+            }
 #pragma unroll 1
             for (int j0 = 0; j0 < kL1Iter; j0 += kL1Batch) {
                 u32x4 bv[kL1Batch];
@@ -404,26 +420,24 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
                 for (int b = 0; b < kL1Batch; ++b) {
                     const int p = (wave + kWaves * (j0 + b)) * 16 + col;
                     const int pc = p < NP ? p : NP - 1;
-                    const int y = pc / RO, x = pc - y * RO;
+                    const int y = pc / RO;
+                    const int base = pc + (kRF - RO) * y;          // feature index of tap 0
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int t = 4 * q + i;                // this lane's slots 8q .. 8q+7
-                        uint32_t v = 0;
-                        if (t < 9) v = feat[(y + t / 3) * kRF + x + t % 3];
-                        bv[b][i] = v;
+                        const uint32_t v = feat[base + toff[i]];
+                        bv[b][i] = tuse[i] ? v : 0u;
                     }
                 }
 #pragma unroll
                 for (int b = 0; b < kL1Batch; ++b) {
-                    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-                    const f32x4 a0 = mfma(w1[0], bv[b], z), a1 = mfma(w1[1], bv[b], z);
+                    const f32x4 a0 = mfma(w1[0], bv[b], bs[0]), a1 = mfma(w1[1], bv[b], bs[1]);
                     const int p = (wave + kWaves * (j0 + b)) * 16 + col;
                     if (p < NP) {
                         const int y = p / RO, x = p - y * RO;
                         const int gx = x0 - 5 + x, gy = y0 - 5 + y;
                         int o0, o1;
                         act_offsets(x, q, o0, o1);
-                        store_act(bufA + p * 64, o0, o1, gx >= 0 && gx < W && gy >= 0 && gy < H, a0, a1, bs);
+                        store_act(bufA + p * 64, o0, o1, gx >= 0 && gx < W && gy >= 0 && gy < H, a0, a1);
                     }
                 }
             }
@@ -490,8 +504,8 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             auto compute = [&](int st) {
                 load_row(2 * st + 2);
                 load_row(2 * st + 3);
-                acc[st][0] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                acc[st][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                acc[st][0] = (f32x4){b6, b6, b6, b6};
+                acc[st][1] = (f32x4){b6, b6, b6, b6};
 #pragma unroll
                 for (int t = 0; t < 9; ++t)
 #pragma unroll
@@ -503,7 +517,7 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
                     const int ly = r0 + 2 * st + k, gy = y0 + ly;
                     if (col_in && gy < H) {
                         const float mu = s_mu[ly * kFT + x];
-                        const float yv = acc[st][k][0] + b6;
+                        const float yv = acc[st][k][0];
                         A.out[(int64_t)gy * A.ld_out + gx] = (mu == mu) ? mu + A.s * yv : __builtin_nanf("");
                     }
                 }
