@@ -398,6 +398,7 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             __syncthreads();                              // every wave holds layer 1's weights
             stage_store(wbuf, 2, tid, r);
             stage_fetch(a, 3, tid, r);
+            __syncthreads();                              // layer-2 weights in LDS
             // groups of 16 consecutive region pixels, group g to wave g % 8, taken
             // kL1Batch at a time so that their feature reads are in flight together
             constexpr int RO = kRA, NP = RO * RO, NG = (NP + 15) / 16;
@@ -442,25 +443,28 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
                 }
             }
         }
-        __syncthreads();                                  // layer 1 out and layer-2 weights ready
+        // Each wave takes the next layer's weights from LDS as soon as its own
+        // part of a layer is done; the barrier after that marks both the layer's
+        // output and every wave's weights ready, the stage store that follows
+        // refills the weight buffer, and one more barrier publishes it.
         load_mid_weights(wbuf, q, col, wa, bs);
-        __syncthreads();
+        __syncthreads();                                  // layer 1 out, layer-2 weights taken
         stage_store(wbuf, 3, tid, r);
         stage_fetch(a, 4, tid, r);
-        mid_layer<kRA>(bufA, bufB, wa, bs, x0 - 4, y0 - 4, W, H, lane, wave);
         __syncthreads();
+        mid_layer<kRA>(bufA, bufB, wa, bs, x0 - 4, y0 - 4, W, H, lane, wave);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 4, tid, r);
         stage_fetch(a, 5, tid, r);
-        mid_layer<kRB>(bufB, bufA, wa, bs, x0 - 3, y0 - 3, W, H, lane, wave);
         __syncthreads();
+        mid_layer<kRB>(bufB, bufA, wa, bs, x0 - 3, y0 - 3, W, H, lane, wave);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 5, tid, r);
         stage_fetch(a, 6, tid, r);
-        mid_layer<kRB - 2>(bufA, bufB, wa, bs, x0 - 2, y0 - 2, W, H, lane, wave);
         __syncthreads();
+        mid_layer<kRB - 2>(bufA, bufB, wa, bs, x0 - 2, y0 - 2, W, H, lane, wave);
         load_mid_weights(wbuf, q, col, wa, bs);
         __syncthreads();
         stage_store(wbuf, 6, tid, r);
@@ -472,8 +476,8 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
             decode_item<BATCH>(a, frames, tile_off, tile_frame, next, An, ntx_, nty_);
             feat_fetch(An, ntx_, nty_, tid, f);
         }
-        mid_layer<kRB - 4>(bufB, bufA, wa, bs, x0 - 1, y0 - 1, W, H, lane, wave);
         __syncthreads();
+        mid_layer<kRB - 4>(bufB, bufA, wa, bs, x0 - 1, y0 - 1, W, H, lane, wave);
 
         // ---- layer 6: 32 -> 1 on the 24 x 24 tile, strips as in the middle layers
         {
@@ -482,8 +486,8 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
 #pragma unroll
             for (int t = 0; t < 9; ++t) w6[t] = lds16(wbuf, t * 16 + col, q);
             const float b6 = reinterpret_cast<const float *>(wbuf + kWBias)[0];
-            __syncthreads();                              // every wave holds layer 6's weights
-            stage_store(wbuf, 1, tid, r);
+            __syncthreads();                              // layer 5 out, layer-6 weights taken
+            stage_store(wbuf, 1, tid, r);                 // read after the next two barriers
             stage_fetch(a, 2, tid, r);
             // three steps of two rows for every wave, pipelined as in mid_layer
             static_assert(RO / 2 == 4 * 3, "layer-6 strip runs");
