@@ -120,9 +120,11 @@ __device__ inline snx_point make_point(int u, int v, float D, float nx, float ny
     snx_point p;
     const bool def = valid_disp(D) && (nx == nx);
     if (def) {
-        const float z = (fx * b) / D;
-        p.x = ((float)u - u0) * z / fx;
-        p.y = ((float)v - v0) * z / fy;
+        // reciprocals (about 1 ulp each) instead of IEEE divisions: the record
+        // is a few ulp from the correctly rounded quotients
+        const float z = (fx * b) * __builtin_amdgcn_rcpf(D);
+        p.x = ((float)u - u0) * z * __builtin_amdgcn_rcpf(fx);
+        p.y = ((float)v - v0) * z * __builtin_amdgcn_rcpf(fy);
         p.z = z;
         p.nx = nx; p.ny = ny; p.nz = nz;
     } else {

@@ -199,11 +199,13 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     }
     __syncthreads();
     // column moments: the first row of a pair by direct sums, the second by
-    // sliding the window down one row
-    for (int j = 0; px_row + 8 * j < th; ++j) {
+    // sliding the window down one row.  The pairs are unrolled for the static
+    // tile heights so that the per-pair label registers are indexed statically.
+    auto pair = [&](int j) {
         const int ty0 = px_row + 8 * j, tx = px_col;
         const int eo = ty0 * kTileW + tx;
         ColMom m = col_moments<RG, true>(sAB + eo, sS + eo, kTileW, rg);
+#pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int ty = ty0 + h;
             if (h == 1) {
@@ -265,6 +267,13 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
                 store_point(a.rec + (int64_t)gy * a.W + gx, p);
             }
         }
+    };
+    if (TH > 0) {
+#pragma unroll
+        for (int j = 0; j < kPairs; ++j)
+            if (px_row + 8 * j < th) pair(j);
+    } else {
+        for (int j = 0; px_row + 8 * j < th; ++j) pair(j);
     }
     if (a.count) {
         __syncthreads();
