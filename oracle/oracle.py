@@ -11,6 +11,8 @@ Stage functions (the C file cites the paper's passage for each):
   normals(Dt, a1, a2, ...)  normal from the constraint-vector cross product
   components(D, k, t)       min-index labels of covered-depth components
   point_cloud(Dt, n, cam)   back-projected points with normals
+  star_mask(Dt, u, v, ...)  star-fill support of one pixel (adaptive region)
+  star_affine(Dt, ...)      a1, a2 and definedness over the star-fill support
   pipeline(D, cam, ...)     all of the above, in order
 """
 from __future__ import annotations
@@ -46,8 +48,12 @@ def load():
                                     C.POINTER(C.c_int64)]
     lib.snxo_point_cloud.argtypes = [_dp, _dp, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
     lib.snxo_num_threads.argtypes = []
+    lib.snxo_star_mask.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                   C.c_int, C.c_double, C.c_double, _u8]
+    lib.snxo_star_affine.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_double, C.c_double, C.c_int, _dp, _dp, _u8]
     for f in ("snxo_denoise", "snxo_affine", "snxo_normals", "snxo_components",
-              "snxo_point_cloud", "snxo_num_threads"):
+              "snxo_point_cloud", "snxo_num_threads", "snxo_star_mask", "snxo_star_affine"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -115,6 +121,47 @@ def point_cloud(Dt, nrm, cam) -> np.ndarray:
     load().snxo_point_cloud(Dt, _as_f64(nrm), W, H, cam.fx, cam.fy,
                             cam.baseline, cam.u0, cam.v0, out)
     return out
+
+
+STOP_CD, STOP_ST = 0, 1
+
+
+def _fxb(cam):
+    """f_x * baseline in binary64 from the float32 camera fields."""
+    if cam is None:
+        return 1.0
+    return float(np.float32(cam.fx)) * float(np.float32(cam.baseline))
+
+
+def star_mask(Dt, u: int, v: int, dirs: int = 8, steps: int = 10, stop: int = STOP_CD,
+              thr: float = 0.05, cam=None):
+    """Support of the star-fill at pixel (u, v) as a (2s+1)^2 boolean array
+    indexed [dy + s, dx + s] (centre not marked), or None for an invalid centre."""
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    side = 2 * steps + 1
+    m = np.zeros(side * side, np.uint8)
+    n = load().snxo_star_mask(Dt, W, H, int(u), int(v), int(dirs), int(steps), int(stop),
+                              float(thr), _fxb(cam), m)
+    if n < 0:
+        return None
+    return m.reshape(side, side).astype(bool)
+
+
+def star_affine(Dt, dirs: int = 8, steps: int = 10, stop: int = STOP_CD, thr: float = 0.05,
+                cam=None, min_support: int = 0):
+    """a1, a2 and definedness over the star-fill support; min_support <= 0
+    selects the default (the number of directions)."""
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    ms = int(dirs) if min_support <= 0 else int(min_support)
+    a1 = np.empty_like(Dt)
+    a2 = np.empty_like(Dt)
+    d = np.empty((H, W), np.uint8)
+    if load().snxo_star_affine(Dt, W, H, int(dirs), int(steps), int(stop), float(thr),
+                               _fxb(cam), ms, a1, a2, d) != 0:
+        raise ValueError("oracle star_affine: bad arguments")
+    return a1, a2, d.astype(bool)
 
 
 def pipeline(D, cam, nf: int = 3, ng: int = 9, min_support_f: int = 0,

@@ -29,6 +29,10 @@
  *                       predicate (Sec. 3.4, CD), labels = minimum linear index,
  *                       breadth-first flood fill in raster order
  *   snxo_point_cloud    X from the rectified projections of Sec. 2 plus n
+ *   snxo_star_mask,     the adaptive star-fill support of Sec. 3.4 (Adaptive
+ *   snxo_star_affine    Region Estimation: rays in M directions with the ST or
+ *                       CD stopping rule) and a1, a2 over it by the two-pass
+ *                       anchored LSQ
  */
 #include <math.h>
 #include <stdint.h>
@@ -288,6 +292,145 @@ int snxo_point_cloud(const double *Dt, const double *nrm, int W, int H,
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive star-fill support (Sec. 3.4, Adaptive Region Estimation).        */
+/* From a valid centre c, rays leave in M = 4 or 8 directions e_m: the       */
+/* directions at angles 2 pi m / M scaled so that their larger component is  */
+/* 1, i.e. the compass directions (for M = 8 the axes and the diagonals, for */
+/* M = 4 the axes).  Ray m takes the pixels c + k e_m, k = 1 .. steps, in    */
+/* order, and stops before the first one that is invalid or outside the      */
+/* image or meets the stopping rule:                                         */
+/*   CD  covered depth: with a, b the smallest and the largest disparity of  */
+/*       c and of the ray's pixels up to and including the new one, stop     */
+/*       when D_c (b - a) > k (a b): the depth range f_x B (1/a - 1/b)        */
+/*       exceeds k times the depth f_x B / D_c of c (binary64, no            */
+/*       contraction; b - a, a b and D_c (b - a) are exact);                 */
+/*   ST  simple threshold on the depth Laplacian: stop when                  */
+/*       L = ((z_r + z_l) + (z_d + z_u)) - 4 z  at the new pixel, with        */
+/*       z = fxb / D (binary64), is undefined (a 4-neighbour invalid or       */
+/*       outside the image) or |L| > t.                                       */
+/* The support is the set of pixels taken by the rays; c anchors the fit.    */
+/* ------------------------------------------------------------------------ */
+#define SNXO_STOP_CD 0
+#define SNXO_STOP_ST 1
+
+static const int kStarDir8[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1},
+                                    {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+
+static int star_valid_at(const double *Dt, int W, int H, int u, int v)
+{
+    return u >= 0 && u < W && v >= 0 && v < H && is_valid(Dt[(int64_t)v * W + u]);
+}
+
+/* 1 iff the depth Laplacian at (u, v) is undefined or exceeds t in magnitude */
+static int star_st_edge(const double *Dt, int W, int H, int u, int v, double fxb, double t)
+{
+    static const int nb[4][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}};
+    for (int i = 0; i < 4; ++i)
+        if (!star_valid_at(Dt, W, H, u + nb[i][0], v + nb[i][1])) return 1;
+    const double zc = fxb / Dt[(int64_t)v * W + u];
+    const double zr = fxb / Dt[(int64_t)v * W + u + 1];
+    const double zl = fxb / Dt[(int64_t)v * W + u - 1];
+    const double zd = fxb / Dt[(int64_t)(v + 1) * W + u];
+    const double zu = fxb / Dt[(int64_t)(v - 1) * W + u];
+    const double L = ((zr + zl) + (zd + zu)) - 4.0 * zc;
+    return fabs(L) > t;
+}
+
+/* Marks the support of centre (u, v) in mask[(dy + s) * (2s + 1) + dx + s]
+ * (the centre itself is not marked) and returns the number of marked pixels,
+ * or -1 for bad arguments or an invalid centre. */
+int snxo_star_mask(const double *Dt, int W, int H, int u, int v, int dirs, int steps,
+                   int stop, double thr, double fxb, uint8_t *mask)
+{
+    if ((dirs != 4 && dirs != 8) || steps < 1 || (stop != SNXO_STOP_CD && stop != SNXO_STOP_ST))
+        return -1;
+    const int side = 2 * steps + 1;
+    memset(mask, 0, (size_t)side * side);
+    if (!star_valid_at(Dt, W, H, u, v)) return -1;
+    const double Dc = Dt[(int64_t)v * W + u];
+    int count = 0;
+    for (int m = 0; m < dirs; ++m) {
+        const int *e = kStarDir8[m * (8 / dirs)];
+        double a = Dc, b = Dc;
+        for (int k = 1; k <= steps; ++k) {
+            const int uu = u + k * e[0], vv = v + k * e[1];
+            if (!star_valid_at(Dt, W, H, uu, vv)) break;
+            const double Di = Dt[(int64_t)vv * W + uu];
+            if (stop == SNXO_STOP_CD) {
+                const double na = Di < a ? Di : a, nbv = Di > b ? Di : b;
+                if (Dc * (nbv - na) > thr * (na * nbv)) break;
+                a = na;
+                b = nbv;
+            } else if (star_st_edge(Dt, W, H, uu, vv, fxb, thr)) {
+                break;
+            }
+            uint8_t *mk = &mask[(k * e[1] + steps) * side + k * e[0] + steps];
+            if (!*mk) { *mk = 1; ++count; }
+        }
+    }
+    return count;
+}
+
+/* a1, a2 and definedness over the star-fill support: the anchored LSQ of
+ * snxo_affine with the window replaced by the support (pass 1: alpha, beta,
+ * gamma; pass 2: the weighted sums).  defined iff the centre is valid, the
+ * support holds >= min_support pixels and alpha gamma - beta^2 > 0. */
+int snxo_star_affine(const double *Dt, int W, int H, int dirs, int steps, int stop,
+                     double thr, double fxb, int min_support, double *a1, double *a2,
+                     uint8_t *defined)
+{
+    if ((dirs != 4 && dirs != 8) || steps < 1 || steps > 64 || W < 1 || H < 1 ||
+        (stop != SNXO_STOP_CD && stop != SNXO_STOP_ST))
+        return 1;
+    const int side = 2 * steps + 1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        uint8_t *mask = (uint8_t *)malloc((size_t)side * side);
+        if (!mask) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int v = 0; v < H; ++v) {
+            for (int u = 0; u < W; ++u) {
+                const int64_t c = (int64_t)v * W + u;
+                a1[c] = NAN; a2[c] = NAN; defined[c] = 0;
+                if (!mask) continue;
+                const int count = snxo_star_mask(Dt, W, H, u, v, dirs, steps, stop, thr, fxb, mask);
+                if (count < 0) continue;
+                const double dc = -Dt[c];
+                int64_t alpha = 0, beta = 0, gamma = 0;
+                for (int dy = -steps; dy <= steps; ++dy)
+                    for (int dx = -steps; dx <= steps; ++dx) {
+                        if (!mask[(dy + steps) * side + dx + steps]) continue;
+                        alpha += (int64_t)dx * dx;
+                        beta += (int64_t)dx * dy;
+                        gamma += (int64_t)dy * dy;
+                    }
+                const int64_t det = alpha * gamma - beta * beta;
+                if (count < min_support || det <= 0) continue;
+                double sum1 = 0.0, sum2 = 0.0;
+                for (int dy = -steps; dy <= steps; ++dy)
+                    for (int dx = -steps; dx <= steps; ++dx) {
+                        if (!mask[(dy + steps) * side + dx + steps]) continue;
+                        const double di = -Dt[(int64_t)(v + dy) * W + u + dx];
+                        const double s1 = ((double)gamma * dx - (double)beta * dy) / (double)det;
+                        const double s2 = (-(double)beta * dx + (double)alpha * dy) / (double)det;
+                        sum1 += s1 * (di - dc);
+                        sum2 += s2 * (di - dc);
+                    }
+                a1[c] = 1.0 + sum1;
+                a2[c] = sum2;
+                defined[c] = 1;
+            }
+        }
+        free(mask);
+    }
+    return fail;
 }
 
 int snxo_num_threads(void)
