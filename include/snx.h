@@ -139,6 +139,46 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride,
                               void *stream);
 
 /* ---------------------------------------------------------------------------
+ * snx_affine_normals_star -- gradients, A and normals over the adaptive
+ * star-fill support of Sec. 3.4 (Adaptive Region Estimation) instead of a
+ * square window.  From a valid centre c, rays leave in `directions` = 4 (the
+ * axes) or 8 (axes and diagonals) directions -- the angles 2 pi m / directions
+ * with the step scaled to a unit larger component -- and take c + k e_m,
+ * k = 1 .. steps (1..32), stopping before the first pixel that is invalid or
+ * outside the image or meets the stopping rule:
+ *   SNX_STOP_CD  covered depth: with a, b the smallest and largest disparity of
+ *                c and of the ray's pixels so far including the new one, stop
+ *                when D_c (b - a) > threshold (a b), i.e. when the depth range
+ *                f_x B (1/a - 1/b) exceeds `threshold` times the depth of c;
+ *   SNX_STOP_ST  simple threshold on the depth Laplacian: stop when
+ *                ((z_r + z_l) + (z_d + z_u)) - 4 z, z = f_x B / D, at the new
+ *                pixel is undefined (a 4-neighbour invalid or outside) or its
+ *                magnitude exceeds `threshold` (baseline units).
+ * Both rules are evaluated in binary64 on the float32 disparities.  The slope
+ * is the anchored LSQ of snx_normal_params over the pixels the rays take (the
+ * centre anchors it); it is defined iff they number at least min_support
+ * (<= 0 selects `directions`) and alpha*gamma - beta^2 > 0.  A and the normal
+ * follow as in snx_affine_normals, and the buffers are laid out the same way.
+ * Other direction counts return SNX_ERR_UNSUPPORTED; steps outside 1..32, an
+ * unknown rule or a negative or non-finite threshold return SNX_ERR_ARG.
+ * ------------------------------------------------------------------------- */
+#define SNX_STOP_CD 0
+#define SNX_STOP_ST 1
+typedef struct snx_star_params {
+    int32_t directions;   /* 4 or 8 */
+    int32_t steps;        /* 1 .. 32 pixels per ray */
+    int32_t stop;         /* SNX_STOP_CD or SNX_STOP_ST */
+    int32_t min_support;  /* <= 0: directions */
+    double threshold;     /* CD: k (e.g. 0.05); ST: t in baseline units */
+} snx_star_params;
+snx_status snx_affine_normals_star(const float *disp_dn, int64_t stride,
+                                   int32_t width, int32_t height,
+                                   const snx_camera *cam,
+                                   const snx_star_params *params,
+                                   float *affine, float *normals, int64_t out_stride,
+                                   void *stream);
+
+/* ---------------------------------------------------------------------------
  * snx_components -- connected surface components of the RAW disparity under the
  * predicate of snx_component_params.  labels[v * label_stride + u] receives the
  * smallest linear index v' * width + u' of the pixel's component, or -1 if the

@@ -53,6 +53,14 @@ class snx_normal_params(C.Structure):
     _fields_ = [("window", C.c_int32), ("min_support", C.c_int32)]
 
 
+class snx_star_params(C.Structure):
+    _fields_ = [("directions", C.c_int32), ("steps", C.c_int32), ("stop", C.c_int32),
+                ("min_support", C.c_int32), ("threshold", C.c_double)]
+
+
+STOP_CD, STOP_ST = 0, 1
+
+
 class snx_component_params(C.Structure):
     _fields_ = [("k_rel", C.c_float), ("t_abs", C.c_float)]
 
@@ -66,6 +74,8 @@ SIGNATURES = {
     "snx_denoise": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_denoise_params), _P]),
     "snx_affine_normals": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                   C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
+    "snx_affine_normals_star": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                                       C.POINTER(snx_star_params), _P, _P, _I64, _P]),
     "snx_components_workspace_size": (_SZ, [_I32, _I32]),
     "snx_components": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_component_params), _P, _I64,
                               _P, _P, _SZ, _P]),
@@ -200,6 +210,23 @@ def snx_affine_normals(disp_dn, cam, affine=None, normals=None, window=9, min_su
     c = camera(cam)
     _check(load().snx_affine_normals(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
                                      _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
+
+
+def snx_affine_normals_star(disp_dn, cam, affine=None, normals=None, directions=8, steps=10,
+                            stop=STOP_CD, threshold=0.05, min_support=0, stream=None):
+    """Gradients, A and normals over the adaptive star-fill support."""
+    import torch
+    H, W = disp_dn.shape
+    ld = _img(disp_dn, torch.float32, "disp_dn")
+    la = _planes(affine, 2, H, W, "affine")
+    ln = _planes(normals, 3, H, W, "normals")
+    if la is not None and ln is not None and la != ln:
+        raise ValueError("affine and normals must share one row stride")
+    out_ld = la if la is not None else (ln if ln is not None else W)
+    p = snx_star_params(directions, steps, stop, min_support, threshold)
+    c = camera(cam)
+    _check(load().snx_affine_normals_star(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
+                                          _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
 
 
 def snx_components_workspace_size(width, height):

@@ -1,6 +1,7 @@
 // C ABI of libsnx: argument validation, workspace carving and kernel launches.
 // Every entry point validates all arguments before the first HIP call, so an
 // invalid call enqueues nothing and writes nothing.
+#include <cmath>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -192,6 +193,52 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride, int32_t widt
     a.plane_out = out_stride * (int64_t)height;
     hipError_t e = snx::launch_stencil(a, (hipStream_t)stream);
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals");
+}
+
+snx_status snx_affine_normals_star(const float *disp_dn, int64_t stride, int32_t width,
+                                   int32_t height, const snx_camera *cam,
+                                   const snx_star_params *params, float *affine, float *normals,
+                                   int64_t out_stride, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (!params) return fail(SNX_ERR_ARG, "params is NULL");
+    if (params->directions <= 0) return fail(SNX_ERR_ARG, "directions %d", params->directions);
+    if (params->directions != 4 && params->directions != 8)
+        return fail(SNX_ERR_UNSUPPORTED, "directions %d (4 or 8 supported)", params->directions);
+    if (params->steps < 1 || params->steps > 32)
+        return fail(SNX_ERR_ARG, "steps %d outside 1..32", params->steps);
+    if (params->stop != SNX_STOP_CD && params->stop != SNX_STOP_ST)
+        return fail(SNX_ERR_ARG, "unknown stopping rule %d", params->stop);
+    if (!std::isfinite(params->threshold) || params->threshold < 0.0)
+        return fail(SNX_ERR_ARG, "threshold must be finite and >= 0");
+    if (!cam_ok(cam)) return fail(SNX_ERR_ARG, "camera is NULL or not finite/positive");
+    if (width == 0 || height == 0) return SNX_OK;
+    snx_status st;
+    if ((st = check_image(disp_dn, stride, width, "disp_dn"))) return st;
+    if (!affine && !normals) return fail(SNX_ERR_ARG, "affine and normals are both NULL");
+    if (out_stride < width) return fail(SNX_ERR_ARG, "out_stride < width");
+    snx::StarArgs a;
+    a.src = disp_dn;
+    a.ld_src = stride;
+    a.W = width;
+    a.H = height;
+    a.dirs = params->directions;
+    a.steps = params->steps;
+    a.stop = params->stop == SNX_STOP_CD ? snx::kStopCD : snx::kStopST;
+    a.need_g = params->min_support > 0 ? params->min_support : params->directions;
+    a.thr = params->threshold;
+    a.fxb = (double)cam->fx * (double)cam->baseline;
+    a.fx = cam->fx;
+    a.fy = cam->fy;
+    a.u0 = cam->u0;
+    a.v0 = cam->v0;
+    a.aff = affine;
+    a.nrm = normals;
+    a.ld_out = out_stride;
+    a.plane_out = out_stride * (int64_t)height;
+    hipError_t e = snx::launch_star(a, (hipStream_t)stream);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals_star");
 }
 
 size_t snx_components_workspace_size(int32_t width, int32_t height) { return ws_components(width, height); }

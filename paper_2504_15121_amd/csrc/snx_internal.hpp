@@ -48,6 +48,23 @@ bool set_tile_height(int rf, int rg, int W, int H, int th);
 hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H, hipStream_t s,
                             int *chosen);
 
+// Adaptive star-fill support (Sec. 3.4): rays in 4 or 8 compass directions,
+// covered-depth or depth-Laplacian stopping, slope, A and normal (star.hip).
+constexpr int kStopCD = 0, kStopST = 1;
+struct StarArgs {
+    const float *src;      // denoised disparity
+    int64_t ld_src;
+    int W, H;
+    int dirs, steps, stop, need_g;
+    double thr;            // k of the CD rule, or t of the ST rule
+    double fxb;            // f_x * baseline (ST)
+    float fx, fy, u0, v0;
+    float *aff, *nrm;      // nullable planes
+    int64_t ld_out, plane_out;
+};
+size_t star_lds_bytes(int steps, int stop);
+hipError_t launch_star(const StarArgs &a, hipStream_t s);
+
 // Front of the pipeline: local components forest of each 64 x 32 tile plus the
 // filter (window 1 or 3) of the same tile, from one read of the raw disparity.
 struct FrontArgs {

@@ -1,0 +1,172 @@
+// Adaptive star-fill support (Sec. 3.4, Adaptive Region Estimation) -> slope,
+// A and normal, for one 64 x 16 output tile per 256-thread workgroup.
+//
+// From a valid centre c, rays leave in the 4 (axes) or 8 (axes and diagonals)
+// compass directions -- the directions 2 pi m / M scaled to a unit larger
+// component -- and take c + k e_m, k = 1 .. steps, stopping before the first
+// pixel that is invalid or outside the image or meets the stopping rule:
+//   CD  D_c (b - a) > k_cd (a b), with a, b the smallest and largest disparity
+//       of c and the ray's pixels so far including the new one (the depth
+//       range f B (1/a - 1/b) exceeds k_cd times the depth of c), binary64;
+//   ST  the 4-neighbour depth Laplacian ((z_r + z_l) + (z_d + z_u)) - 4 z with
+//       z = f_x B / D (binary64) at the new pixel is undefined or exceeds t in
+//       magnitude.
+// The slope is the anchored LSQ over the pixels the rays take (the two-pass
+// scheme of Sec. 3.4 with the star as the support), then A and the normal as
+// for the square windows.
+//
+// The rays of the compass directions never share a pixel, so a ray's moments
+// follow from its length n alone (sum k = n(n+1)/2, sum k^2 = n(n+1)(2n+1)/6
+// times the direction's components) plus one exact FP64 sum of k D per ray.
+// The tile (validity-coded, halo = steps, + 1 for ST) and, for ST, a byte
+// plane of edge flags sit in LDS.
+#include "lsq.hpp"
+
+namespace snx {
+namespace {
+
+constexpr int kStW = 64, kStH = 16, kStBlock = 256;
+
+// compass directions in the order of the angle 2 pi m / 8 (v downwards)
+__device__ __forceinline__ constexpr int dir_x(int m) { return m == 0 || m == 1 || m == 7 ? 1 : (m == 2 || m == 6 ? 0 : -1); }
+__device__ __forceinline__ constexpr int dir_y(int m) { return m == 1 || m == 2 || m == 3 ? 1 : (m == 0 || m == 4 ? 0 : -1); }
+
+template <int M, int STOP>
+__global__ void __launch_bounds__(kStBlock)
+k_star(StarArgs a)
+{
+#pragma clang fp contract(off)
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int s = a.steps;
+    const int R = s + (STOP == kStopST ? 1 : 0);     // halo of the value tile
+    const int LW = kStW + 2 * R, LH = kStH + 2 * R;
+    float *sD = reinterpret_cast<float *>(smem);
+    const int EW = kStW + 2 * s, EH = kStH + 2 * s;   // edge flags: halo s
+    unsigned char *sE = smem + sizeof(float) * (size_t)LW * LH;
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * kStW, y0 = blockIdx.y * kStH;
+
+    for (int e = tid; e < LW * LH; e += kStBlock) {
+        const int ly = e / LW, lx = e - ly * LW;
+        const int gy = y0 - R + ly, gx = x0 - R + lx;
+        float v = 0.0f;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+            const float d = a.src[(int64_t)gy * a.ld_src + gx];
+            v = valid_disp(d) ? d : 0.0f;
+        }
+        sD[e] = v;
+    }
+    __syncthreads();
+    if (STOP == kStopST) {
+        for (int e = tid; e < EW * EH; e += kStBlock) {
+            const int ey = e / EW, ex = e - ey * EW;
+            const float *p = sD + (ey + 1) * LW + ex + 1;       // same pixel in the value tile
+            const float c = p[0], r = p[1], l = p[-1], d = p[LW], u = p[-LW];
+            unsigned char edge = 1;
+            if (c > 0.0f && r > 0.0f && l > 0.0f && d > 0.0f && u > 0.0f) {
+                const double zc = a.fxb / (double)c, zr = a.fxb / (double)r;
+                const double zl = a.fxb / (double)l, zd = a.fxb / (double)d;
+                const double zu = a.fxb / (double)u;
+                const double L = ((zr + zl) + (zd + zu)) - 4.0 * zc;
+                edge = fabs(L) > a.thr ? 1 : 0;
+            }
+            sE[e] = edge;
+        }
+        __syncthreads();
+    }
+
+    const int tx = tid & 63;
+    for (int ty = tid >> 6; ty < kStH; ty += kStBlock / 64) {
+        const int gx = x0 + tx, gy = y0 + ty;
+        if (gx >= a.W || gy >= a.H) continue;
+        const int pc = (ty + R) * LW + tx + R;
+        const int ec = (ty + s) * EW + tx + s;
+        const float Dc = sD[pc];
+        float nx = __builtin_nanf(""), ny = nx, nz = nx, a1 = nx, a2 = nx;
+        if (Dc > 0.0f) {
+            int N = 1, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
+            double Rx = 0.0, Ry = 0.0;
+#pragma unroll
+            for (int mi = 0; mi < M; ++mi) {
+                const int m = mi * (8 / M);
+                const int ex = dir_x(m), ey = dir_y(m);
+                const int dp = ey * LW + ex, de = ey * EW + ex;
+                float lo = Dc, hi = Dc;
+                double wk = 0.0;
+                int n = 0;
+                for (int k = 1; k <= s; ++k) {
+                    const float v = sD[pc + k * dp];
+                    if (!(v > 0.0f)) break;
+                    if (STOP == kStopCD) {
+                        const float nlo = v < lo ? v : lo, nhi = v > hi ? v : hi;
+                        const double da = (double)nlo, db = (double)nhi;
+                        if ((double)Dc * (db - da) > a.thr * (da * db)) break;
+                        lo = nlo;
+                        hi = nhi;
+                    } else if (sE[ec + k * de]) {
+                        break;
+                    }
+                    wk += (double)k * (double)v;
+                    n = k;
+                }
+                const int t1 = n * (n + 1) / 2, t2 = n * (n + 1) * (2 * n + 1) / 6;
+                N += n;
+                Sx += ex * t1;
+                Sy += ey * t1;
+                Sxx += ex * ex * t2;
+                Sxy += ex * ey * t2;
+                Syy += ey * ey * t2;
+                Rx += (double)ex * wk;
+                Ry += (double)ey * wk;
+            }
+            ColMom mo;
+            mo.N = N; mo.Sx = Sx; mo.Sy = Sy; mo.Sxx = Sxx; mo.Sxy = Sxy; mo.Syy = Syy;
+            mo.R0 = 0.0; mo.Rx = Rx; mo.Ry = Ry;
+            double gu, gv;
+            if (slope_solve(mo, Dc, a.need_g, gu, gv)) {
+                a1 = (float)(1.0 - gu);
+                a2 = (float)(-gv);
+                normal_from_slope(gu, gv, Dc, gx, gy, a.fx, a.fy, a.u0, a.v0, nx, ny, nz);
+            }
+        }
+        const int64_t o = (int64_t)gy * a.ld_out + gx;
+        if (a.aff) {
+            a.aff[o] = a1;
+            a.aff[o + a.plane_out] = a2;
+        }
+        if (a.nrm) {
+            a.nrm[o] = nx;
+            a.nrm[o + a.plane_out] = ny;
+            a.nrm[o + 2 * a.plane_out] = nz;
+        }
+    }
+}
+
+}  // namespace
+
+size_t star_lds_bytes(int steps, int stop)
+{
+    const int R = steps + (stop == kStopST ? 1 : 0);
+    size_t b = sizeof(float) * (size_t)(kStW + 2 * R) * (kStH + 2 * R);
+    if (stop == kStopST) b += (size_t)(kStW + 2 * steps) * (kStH + 2 * steps);
+    return b;
+}
+
+hipError_t launch_star(const StarArgs &a, hipStream_t s)
+{
+    const dim3 grid((a.W + kStW - 1) / kStW, (a.H + kStH - 1) / kStH);
+    const size_t lds = star_lds_bytes(a.steps, a.stop);
+    if (a.dirs == 8 && a.stop == kStopCD)
+        hipLaunchKernelGGL((k_star<8, kStopCD>), grid, dim3(kStBlock), lds, s, a);
+    else if (a.dirs == 8 && a.stop == kStopST)
+        hipLaunchKernelGGL((k_star<8, kStopST>), grid, dim3(kStBlock), lds, s, a);
+    else if (a.dirs == 4 && a.stop == kStopCD)
+        hipLaunchKernelGGL((k_star<4, kStopCD>), grid, dim3(kStBlock), lds, s, a);
+    else if (a.dirs == 4 && a.stop == kStopST)
+        hipLaunchKernelGGL((k_star<4, kStopST>), grid, dim3(kStBlock), lds, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace snx

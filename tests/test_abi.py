@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 23
+    assert len(names) == 24
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -97,6 +97,29 @@ def test_affine_normals_validation(lib):
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(ok),
                                   FAKE, FAKE, 32, None) == 1
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, None, C.byref(ok), FAKE, FAKE, 64, None) == 1
+
+
+def test_star_validation(lib):
+    from paper_2504_15121_amd._lib import snx_star_params
+    cam = _cam()
+    ok = snx_star_params(8, 10, 0, 0, 0.05)
+
+    def call(p, w=64, h=8, aff=FAKE, nrm=FAKE, out=64, c=cam):
+        return lib.snx_affine_normals_star(FAKE, 64, w, h, C.byref(c) if c is not None else None,
+                                           C.byref(p) if p is not None else None, aff, nrm, out,
+                                           None)
+    assert call(snx_star_params(16, 10, 0, 0, 0.05)) == 2        # unsupported direction count
+    assert call(snx_star_params(0, 10, 0, 0, 0.05)) == 1
+    assert call(snx_star_params(8, 0, 0, 0, 0.05)) == 1
+    assert call(snx_star_params(8, 33, 0, 0, 0.05)) == 1
+    assert call(snx_star_params(8, 10, 2, 0, 0.05)) == 1
+    assert call(snx_star_params(8, 10, 0, 0, -1.0)) == 1
+    assert call(snx_star_params(8, 10, 1, 0, float("nan"))) == 1
+    assert call(None) == 1
+    assert call(ok, c=None) == 1
+    assert call(ok, aff=None, nrm=None) == 1
+    assert call(ok, out=32) == 1
+    assert call(ok, w=0, h=0) == 0                                # empty call
 
 
 def test_components_validation(lib):
