@@ -17,7 +17,8 @@
 //
 // The rays of the compass directions never share a pixel, so a ray's moments
 // follow from its length n alone (sum k = n(n+1)/2, sum k^2 = n(n+1)(2n+1)/6
-// times the direction's components) plus one exact FP64 sum of k D per ray.
+// times the direction's components) plus one exact FP64 sum of k D per ray;
+// the rays of a pixel advance in lock step.
 // The tile (validity-coded, halo = steps, + 1 for ST) and, for ST, a byte
 // plane of edge flags sit in LDS.
 #include "lsq.hpp"
@@ -84,31 +85,60 @@ k_star(StarArgs a)
         const float Dc = sD[pc];
         float nx = __builtin_nanf(""), ny = nx, nz = nx, a1 = nx, a2 = nx;
         if (Dc > 0.0f) {
+            // The rays advance together, one step per pass: their LDS reads are
+            // in flight at once, and a stopped ray is carried as a predicate
+            // (a stopped ray reads pixels still inside the tile and adds 0).
+            const double dc64 = (double)Dc;
+            float lo[M], hi[M];
+            double wk[M];
+            int nk[M], pp[M], pe[M];
+            bool alive[M];
+#pragma unroll
+            for (int mi = 0; mi < M; ++mi) {
+                lo[mi] = hi[mi] = Dc;
+                wk[mi] = 0.0;
+                nk[mi] = 0;
+                pp[mi] = pc;
+                pe[mi] = ec;
+                alive[mi] = true;
+            }
+            for (int k = 1; k <= s; ++k) {
+                float vv[M];
+#pragma unroll
+                for (int mi = 0; mi < M; ++mi) {
+                    const int m = mi * (8 / M);
+                    pp[mi] += dir_y(m) * LW + dir_x(m);
+                    vv[mi] = sD[pp[mi]];
+                }
+                bool any = false;
+#pragma unroll
+                for (int mi = 0; mi < M; ++mi) {
+                    const int m = mi * (8 / M);
+                    const float v = vv[mi];
+                    bool ok = alive[mi] && v > 0.0f;
+                    if (STOP == kStopCD) {
+                        const float nlo = v < lo[mi] ? v : lo[mi], nhi = v > hi[mi] ? v : hi[mi];
+                        const double da = (double)nlo, db = (double)nhi;
+                        ok = ok && !(dc64 * (db - da) > a.thr * (da * db));
+                        lo[mi] = ok ? nlo : lo[mi];
+                        hi[mi] = ok ? nhi : hi[mi];
+                    } else {
+                        pe[mi] += dir_y(m) * EW + dir_x(m);
+                        ok = ok && !sE[pe[mi]];
+                    }
+                    wk[mi] += ok ? (double)k * (double)v : 0.0;
+                    nk[mi] = ok ? k : nk[mi];
+                    alive[mi] = ok;
+                    any = any || ok;
+                }
+                if (!__any(any)) break;
+            }
             int N = 1, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
             double Rx = 0.0, Ry = 0.0;
 #pragma unroll
             for (int mi = 0; mi < M; ++mi) {
                 const int m = mi * (8 / M);
-                const int ex = dir_x(m), ey = dir_y(m);
-                const int dp = ey * LW + ex, de = ey * EW + ex;
-                float lo = Dc, hi = Dc;
-                double wk = 0.0;
-                int n = 0;
-                for (int k = 1; k <= s; ++k) {
-                    const float v = sD[pc + k * dp];
-                    if (!(v > 0.0f)) break;
-                    if (STOP == kStopCD) {
-                        const float nlo = v < lo ? v : lo, nhi = v > hi ? v : hi;
-                        const double da = (double)nlo, db = (double)nhi;
-                        if ((double)Dc * (db - da) > a.thr * (da * db)) break;
-                        lo = nlo;
-                        hi = nhi;
-                    } else if (sE[ec + k * de]) {
-                        break;
-                    }
-                    wk += (double)k * (double)v;
-                    n = k;
-                }
+                const int ex = dir_x(m), ey = dir_y(m), n = nk[mi];
                 const int t1 = n * (n + 1) / 2, t2 = n * (n + 1) * (2 * n + 1) / 6;
                 N += n;
                 Sx += ex * t1;
@@ -116,8 +146,8 @@ k_star(StarArgs a)
                 Sxx += ex * ex * t2;
                 Sxy += ex * ey * t2;
                 Syy += ey * ey * t2;
-                Rx += (double)ex * wk;
-                Ry += (double)ey * wk;
+                Rx += (double)ex * wk[mi];
+                Ry += (double)ey * wk[mi];
             }
             ColMom mo;
             mo.N = N; mo.Sx = Sx; mo.Sy = Sy; mo.Sxx = Sxx; mo.Sxy = Sxy; mo.Syy = Syy;
