@@ -23,6 +23,12 @@ replay of a captured batch plan (snx_plan_run) per step:
                    sigma = 0.75 px, 10 % invalid): the learned filter batched,
                    and the plain filter batched, with the mean angular error of
                    each against the generator's normals on the distinct frames
+  star_fill        the headline frame's filtered disparity through the square
+                   9x9 window and through the adaptive star-fill support
+                   (8 directions, 10 steps, covered-depth and depth-Laplacian
+                   stopping): time per frame, coverage, mean angular error over
+                   all defined pixels and over the band within 4 px of a surface
+                   boundary
 """
 import argparse
 import hashlib
@@ -54,6 +60,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batch-plan figures")
+    ap.add_argument("--no-star", action="store_true", help="skip the star-fill figures")
     ap.add_argument("--road-frames", type=int, default=256)
     ap.add_argument("--road-distinct", type=int, default=16,
                     help="distinct generated road frames (the rest are copies)")
@@ -257,6 +264,72 @@ def iso_sweep(args):
                   f"{ms:.4f} | {W * H / (ms * 1e-3) / 1e6:.0f} |", flush=True)
 
 
+def bench_star(snx, torch, np, dev, sc, cam, nf):
+    """Square window vs star-fill support on the headline frame (same D~)."""
+    H, W = sc.disp.shape
+    d = torch.from_numpy(sc.disp).to(dev)
+    dn = torch.empty((H, W), device=dev)
+    snx.snx_denoise(d, dn, window=nf)
+    aff = torch.empty((2, H, W), device=dev)
+    nrm = torch.empty((3, H, W), device=dev)
+    # pixels within 4 px of a boundary between two ground-truth surfaces
+    p = sc.patch
+    band = np.zeros((H, W), bool)
+    for dy in range(-4, 5):
+        for dx in range(-4, 5):
+            q = np.full((H, W), -2, p.dtype)
+            q[max(0, -dy):H - max(0, dy), max(0, -dx):W - max(0, dx)] = \
+                p[max(0, dy):H - max(0, -dy), max(0, dx):W - max(0, -dx)]
+            band |= (q != p) & (q != -2)
+    gt = sc.normal
+
+    def timed(fn, n=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(n):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    def errors():
+        n = np.moveaxis(nrm.cpu().numpy(), 0, -1).astype(np.float64)
+        ok = np.isfinite(n[..., 0]) & np.isfinite(gt[..., 0])
+        ang = np.full((H, W), np.nan)
+        cr = np.linalg.norm(np.cross(n[ok], gt[ok]), axis=-1)
+        ang[ok] = np.degrees(np.arctan2(cr, np.abs((n[ok] * gt[ok]).sum(-1))))
+        valid = np.isfinite(gt[..., 0])
+        return (round(float(np.nanmean(ang)), 3), round(float(np.nanmean(ang[band])), 3),
+                round(float(ok.sum() / max(valid.sum(), 1)), 4))
+
+    rows = []
+    configs = [("window", dict(window=9), None)]
+    for thr in (0.05, 0.1, 0.2):
+        configs.append(("star_cd", dict(directions=8, steps=10, stop=snx.STOP_CD, threshold=thr), thr))
+    for thr in (0.5, 2.0):
+        configs.append(("star_st", dict(directions=8, steps=10, stop=snx.STOP_ST, threshold=thr), thr))
+    for kind, kw, thr in configs:
+        if kind == "window":
+            fn = lambda: snx.snx_affine_normals(dn, cam, affine=aff, normals=nrm, **kw)
+        else:
+            fn = lambda: snx.snx_affine_normals_star(dn, cam, affine=aff, normals=nrm, **kw)
+        ms = timed(fn)
+        fn()
+        torch.cuda.synchronize()
+        e_all, e_band, cov = errors()
+        row = {"support": "9x9 window" if kind == "window" else
+               f"star 8 dirs x 10 steps, {'CD k' if kind == 'star_cd' else 'ST t'} = {thr}",
+               "ms_per_frame": round(ms, 4), "mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+               "coverage": cov, "mean_err_deg": e_all, "mean_err_edge_band_deg": e_band}
+        rows.append(row)
+    return {"workload": "planes_quadrics_1920x1080", "filter_window": nf,
+            "edge_band_px": int(band.sum()), "rows": rows}
+
+
 def main():
     args = parse()
     if args.iso_sweep:
@@ -356,6 +429,7 @@ def main():
                 "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(fused_ms, 5)}
 
     batched = None if args.no_batched else bench_batched(args, snx, torch, np, dev, nf, ng)
+    star = None if args.no_star else bench_star(snx, torch, np, dev, sc, cam, nf)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -391,6 +465,8 @@ def main():
     }
     if batched:
         out.update(batched)
+    if star:
+        out["star_fill"] = star
     print(json.dumps(out), flush=True)
 
 
