@@ -11,6 +11,7 @@ Stage functions (the C file cites the paper's passage for each):
   normals(Dt, a1, a2, ...)  normal from the constraint-vector cross product
   components(D, k, t)       min-index labels of covered-depth components
   point_cloud(Dt, n, cam)   back-projected points with normals
+  affine_labels(Dt, lab, ng) a1, a2 over the window restricted to the centre's component
   star_mask(Dt, u, v, ...)  star-fill support of one pixel (adaptive region)
   star_affine(Dt, ...)      a1, a2 and definedness over the star-fill support
   pipeline(D, cam, ...)     all of the above, in order
@@ -48,12 +49,15 @@ def load():
                                     C.POINTER(C.c_int64)]
     lib.snxo_point_cloud.argtypes = [_dp, _dp, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
     lib.snxo_num_threads.argtypes = []
+    lib.snxo_affine_labels.argtypes = [_dp, _i32, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp,
+                                       _u8]
     lib.snxo_star_mask.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_double, C.c_double, _u8]
     lib.snxo_star_affine.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                                      C.c_double, C.c_double, C.c_int, _dp, _dp, _u8]
     for f in ("snxo_denoise", "snxo_affine", "snxo_normals", "snxo_components",
-              "snxo_point_cloud", "snxo_num_threads", "snxo_star_mask", "snxo_star_affine"):
+              "snxo_point_cloud", "snxo_num_threads", "snxo_star_mask", "snxo_star_affine",
+              "snxo_affine_labels"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -121,6 +125,21 @@ def point_cloud(Dt, nrm, cam) -> np.ndarray:
     load().snxo_point_cloud(Dt, _as_f64(nrm), W, H, cam.fx, cam.fy,
                             cam.baseline, cam.u0, cam.v0, out)
     return out
+
+
+def affine_labels(Dt, lab, ng: int, min_support: int | None = None):
+    """a1, a2 and definedness with the n_g window restricted to the pixels of
+    the centre's component (labels as from components())."""
+    Dt = _as_f64(Dt)
+    H, W = Dt.shape
+    ms = default_min_support(ng) if min_support is None else int(min_support)
+    a1 = np.empty_like(Dt)
+    a2 = np.empty_like(Dt)
+    d = np.empty((H, W), np.uint8)
+    if load().snxo_affine_labels(Dt, np.ascontiguousarray(lab, dtype=np.int32), W, H, int(ng),
+                                 ms, a1, a2, d) != 0:
+        raise ValueError("oracle affine_labels: bad arguments")
+    return a1, a2, d.astype(bool)
 
 
 STOP_CD, STOP_ST = 0, 1

@@ -29,6 +29,9 @@
  *                       predicate (Sec. 3.4, CD), labels = minimum linear index,
  *                       breadth-first flood fill in raster order
  *   snxo_point_cloud    X from the rectified projections of Sec. 2 plus n
+ *   snxo_affine_labels  a1, a2 with the n_g window restricted to the centre's
+ *                       surface component (Sec. 3.4's concern about neighbouring
+ *                       surfaces, with the components of snxo_components)
  *   snxo_star_mask,     the adaptive star-fill support of Sec. 3.4 (Adaptive
  *   snxo_star_affine    Region Estimation: rays in M directions with the ST or
  *                       CD stopping rule) and a1, a2 over it by the two-pass
@@ -149,6 +152,63 @@ int snxo_affine(const double *Dt, int W, int H, int ng, int min_support,
                     const double Di = Dt[(int64_t)vv * W + uu];
                     if (!is_valid(Di)) continue;
                     const double di = -Di;
+                    const double s1 = ((double)gamma * dx - (double)beta * dy) / (double)det;
+                    const double s2 = (-(double)beta * dx + (double)alpha * dy) / (double)det;
+                    sum1 += s1 * (di - dc);
+                    sum2 += s2 * (di - dc);
+                }
+            a1[c] = 1.0 + sum1;
+            a2[c] = sum2;
+            defined[c] = 1;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Component-restricted window: as snxo_affine, with neighbour i of the      */
+/* n_g x n_g window taken only if it is valid and lab[i] == lab[c] (labels   */
+/* of the surface components, e.g. from snxo_components; the paper's concern */
+/* that points of a neighbouring surface smooth the normals, Sec. 3.4).      */
+/* A centre with lab < 0 is undefined.                                        */
+/* ------------------------------------------------------------------------ */
+int snxo_affine_labels(const double *Dt, const int32_t *lab, int W, int H, int ng,
+                       int min_support, double *a1, double *a2, uint8_t *defined)
+{
+    if (ng < 3 || (ng % 2) == 0 || W < 1 || H < 1) return 1;
+    const int r = (ng - 1) / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int v = 0; v < H; ++v) {
+        for (int u = 0; u < W; ++u) {
+            const int64_t c = (int64_t)v * W + u;
+            a1[c] = NAN; a2[c] = NAN; defined[c] = 0;
+            if (!is_valid(Dt[c]) || lab[c] < 0) continue;
+            const double dc = -Dt[c];
+            int64_t alpha = 0, beta = 0, gamma = 0;
+            int count = 0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const int uu = u + dx, vv = v + dy;
+                    if (uu < 0 || uu >= W || vv < 0 || vv >= H) continue;
+                    const int64_t i = (int64_t)vv * W + uu;
+                    if (!is_valid(Dt[i]) || lab[i] != lab[c]) continue;
+                    alpha += (int64_t)dx * dx;
+                    beta += (int64_t)dx * dy;
+                    gamma += (int64_t)dy * dy;
+                    ++count;
+                }
+            const int64_t det = alpha * gamma - beta * beta;
+            if (count < min_support || det <= 0) continue;
+            double sum1 = 0.0, sum2 = 0.0;
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    const int uu = u + dx, vv = v + dy;
+                    if (uu < 0 || uu >= W || vv < 0 || vv >= H) continue;
+                    const int64_t i = (int64_t)vv * W + uu;
+                    if (!is_valid(Dt[i]) || lab[i] != lab[c]) continue;
+                    const double di = -Dt[i];
                     const double s1 = ((double)gamma * dx - (double)beta * dy) / (double)det;
                     const double s2 = (-(double)beta * dx + (double)alpha * dy) / (double)det;
                     sum1 += s1 * (di - dc);
