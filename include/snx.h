@@ -139,6 +139,24 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride,
                               void *stream);
 
 /* ---------------------------------------------------------------------------
+ * snx_affine_normals_labels -- snx_affine_normals with the n_g x n_g window
+ * restricted to the centre's surface component: neighbour i is used only if it
+ * is valid and labels[i] == labels[c] (so points of a neighbouring surface do
+ * not smooth the normal, the concern of Sec. 3.4).  labels: [height x
+ * label_stride] int32, e.g. from snx_components on the raw disparity; a centre
+ * with a negative label is undefined.  Window, min_support (counted over the
+ * restricted support), outputs and layout as in snx_affine_normals; windows
+ * above 63 are rejected like there.
+ * ------------------------------------------------------------------------- */
+snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride,
+                                     const int32_t *labels, int64_t label_stride,
+                                     int32_t width, int32_t height,
+                                     const snx_camera *cam,
+                                     const snx_normal_params *params,
+                                     float *affine, float *normals, int64_t out_stride,
+                                     void *stream);
+
+/* ---------------------------------------------------------------------------
  * snx_affine_normals_star -- gradients, A and normals over the adaptive
  * star-fill support of Sec. 3.4 (Adaptive Region Estimation) instead of a
  * square window.  From a valid centre c, rays leave in `directions` = 4 (the

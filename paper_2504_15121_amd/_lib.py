@@ -74,6 +74,8 @@ SIGNATURES = {
     "snx_denoise": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_denoise_params), _P]),
     "snx_affine_normals": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                   C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
+    "snx_affine_normals_labels": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_camera),
+                                         C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
     "snx_affine_normals_star": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                        C.POINTER(snx_star_params), _P, _P, _I64, _P]),
     "snx_components_workspace_size": (_SZ, [_I32, _I32]),
@@ -210,6 +212,27 @@ def snx_affine_normals(disp_dn, cam, affine=None, normals=None, window=9, min_su
     c = camera(cam)
     _check(load().snx_affine_normals(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
                                      _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
+
+
+def snx_affine_normals_labels(disp_dn, labels, cam, affine=None, normals=None, window=9,
+                              min_support=0, stream=None):
+    """Gradients, A and normals over the window restricted to the centre's component."""
+    import torch
+    H, W = disp_dn.shape
+    ld = _img(disp_dn, torch.float32, "disp_dn")
+    ll = _img(labels, torch.int32, "labels")
+    if tuple(labels.shape) != (H, W):
+        raise ValueError("labels must have the shape of disp_dn")
+    la = _planes(affine, 2, H, W, "affine")
+    ln = _planes(normals, 3, H, W, "normals")
+    if la is not None and ln is not None and la != ln:
+        raise ValueError("affine and normals must share one row stride")
+    out_ld = la if la is not None else (ln if ln is not None else W)
+    p = snx_normal_params(window, min_support)
+    c = camera(cam)
+    _check(load().snx_affine_normals_labels(_ptr(disp_dn), ld, _ptr(labels), ll, W, H,
+                                            C.byref(c), C.byref(p), _ptr(affine), _ptr(normals),
+                                            out_ld, _stream(stream)))
 
 
 def snx_affine_normals_star(disp_dn, cam, affine=None, normals=None, directions=8, steps=10,

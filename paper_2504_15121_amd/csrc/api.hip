@@ -195,6 +195,43 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride, int32_t widt
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals");
 }
 
+snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride, const int32_t *labels,
+                                     int64_t label_stride, int32_t width, int32_t height,
+                                     const snx_camera *cam, const snx_normal_params *params,
+                                     float *affine, float *normals, int64_t out_stride,
+                                     void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_normal(params);
+    if (st) return st;
+    if (!cam_ok(cam)) return fail(SNX_ERR_ARG, "camera is NULL or not finite/positive");
+    if (width == 0 || height == 0) return SNX_OK;
+    if ((st = check_image(disp_dn, stride, width, "disp_dn"))) return st;
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    if (!affine && !normals) return fail(SNX_ERR_ARG, "affine and normals are both NULL");
+    if (out_stride < width) return fail(SNX_ERR_ARG, "out_stride < width");
+    snx::RestrictArgs a;
+    a.src = disp_dn;
+    a.ld_src = stride;
+    a.labels = labels;
+    a.ld_lab = label_stride;
+    a.W = width;
+    a.H = height;
+    a.r = params->window / 2;
+    a.need_g = need_g(params);
+    a.fx = cam->fx;
+    a.fy = cam->fy;
+    a.u0 = cam->u0;
+    a.v0 = cam->v0;
+    a.aff = affine;
+    a.nrm = normals;
+    a.ld_out = out_stride;
+    a.plane_out = out_stride * (int64_t)height;
+    hipError_t e = snx::launch_affine_labels(a, (hipStream_t)stream);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals_labels");
+}
+
 snx_status snx_affine_normals_star(const float *disp_dn, int64_t stride, int32_t width,
                                    int32_t height, const snx_camera *cam,
                                    const snx_star_params *params, float *affine, float *normals,

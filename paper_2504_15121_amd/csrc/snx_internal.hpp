@@ -48,6 +48,21 @@ bool set_tile_height(int rf, int rg, int W, int H, int th);
 hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H, hipStream_t s,
                             int *chosen);
 
+// Component-restricted gradient window (restricted.hip): the n_g window keeps
+// only the valid pixels whose label equals the centre's.
+struct RestrictArgs {
+    const float *src;      // denoised disparity
+    int64_t ld_src;
+    const int32_t *labels; // component labels (-1 = none)
+    int64_t ld_lab;
+    int W, H, r, need_g;
+    float fx, fy, u0, v0;
+    float *aff, *nrm;      // nullable planes
+    int64_t ld_out, plane_out;
+};
+size_t restrict_lds_bytes(int r);
+hipError_t launch_affine_labels(const RestrictArgs &a, hipStream_t s);
+
 // Adaptive star-fill support (Sec. 3.4): rays in 4 or 8 compass directions,
 // covered-depth or depth-Laplacian stopping, slope, A and normal (star.hip).
 constexpr int kStopCD = 0, kStopST = 1;

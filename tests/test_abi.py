@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 24
+    assert len(names) == 25
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -97,6 +97,26 @@ def test_affine_normals_validation(lib):
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(ok),
                                   FAKE, FAKE, 32, None) == 1
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, None, C.byref(ok), FAKE, FAKE, 64, None) == 1
+
+
+def test_labels_validation(lib):
+    from paper_2504_15121_amd._lib import snx_normal_params
+    cam = _cam()
+    ok = snx_normal_params(9, 0)
+
+    def call(p=ok, lab=FAKE, ll=64, out=64, c=cam, aff=FAKE, nrm=FAKE, w=64):
+        return lib.snx_affine_normals_labels(FAKE, 64, lab, ll, w, 8,
+                                             C.byref(c) if c is not None else None,
+                                             C.byref(p) if p is not None else None, aff, nrm, out,
+                                             None)
+    assert call(p=snx_normal_params(4, 0)) == 1       # even window
+    assert call(p=snx_normal_params(65, 0)) != 0
+    assert call(lab=None) == 1
+    assert call(ll=32) == 1
+    assert call(c=None) == 1
+    assert call(aff=None, nrm=None) == 1
+    assert call(out=32) == 1
+    assert call(w=0) == 0                             # empty call
 
 
 def test_star_validation(lib):
