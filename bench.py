@@ -23,12 +23,12 @@ replay of a captured batch plan (snx_plan_run) per step:
                    sigma = 0.75 px, 10 % invalid): the learned filter batched,
                    and the plain filter batched, with the mean angular error of
                    each against the generator's normals on the distinct frames
-  star_fill        the headline frame's filtered disparity through the square
-                   9x9 window and through the adaptive star-fill support
-                   (8 directions, 10 steps, covered-depth and depth-Laplacian
-                   stopping): time per frame, coverage, mean angular error over
-                   all defined pixels and over the band within 4 px of a surface
-                   boundary
+  adaptive_support the headline frame's filtered disparity through the square
+                   9x9 window, the 9x9 window restricted to the centre's surface
+                   component, and the adaptive star-fill support (8 directions,
+                   10 steps, covered-depth and depth-Laplacian stopping): time
+                   per frame, coverage, mean angular error over all defined
+                   pixels and over the band within 4 px of a surface boundary
 """
 import argparse
 import hashlib
@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 512 MiB device copy (reference for HBM counters)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batch-plan figures")
-    ap.add_argument("--no-star", action="store_true", help="skip the star-fill figures")
+    ap.add_argument("--no-star", action="store_true",
+                    help="skip the adaptive-support figures (restricted window, star fill)")
     ap.add_argument("--road-frames", type=int, default=256)
     ap.add_argument("--road-distinct", type=int, default=16,
                     help="distinct generated road frames (the rest are copies)")
@@ -265,11 +266,15 @@ def iso_sweep(args):
 
 
 def bench_star(snx, torch, np, dev, sc, cam, nf):
-    """Square window vs star-fill support on the headline frame (same D~)."""
+    """Square window, component-restricted window and star-fill support on the
+    headline frame (same D~)."""
     H, W = sc.disp.shape
     d = torch.from_numpy(sc.disp).to(dev)
     dn = torch.empty((H, W), device=dev)
     snx.snx_denoise(d, dn, window=nf)
+    lab = torch.empty((H, W), dtype=torch.int32, device=dev)
+    cws = torch.empty(snx.snx_components_workspace_size(W, H), dtype=torch.uint8, device=dev)
+    snx.snx_components(d, lab, cws)
     aff = torch.empty((2, H, W), device=dev)
     nrm = torch.empty((3, H, W), device=dev)
     # pixels within 4 px of a boundary between two ground-truth surfaces
@@ -307,7 +312,7 @@ def bench_star(snx, torch, np, dev, sc, cam, nf):
                 round(float(ok.sum() / max(valid.sum(), 1)), 4))
 
     rows = []
-    configs = [("window", dict(window=9), None)]
+    configs = [("window", dict(window=9), None), ("labels", dict(window=9), None)]
     for thr in (0.05, 0.1, 0.2):
         configs.append(("star_cd", dict(directions=8, steps=10, stop=snx.STOP_CD, threshold=thr), thr))
     for thr in (0.5, 2.0):
@@ -315,13 +320,16 @@ def bench_star(snx, torch, np, dev, sc, cam, nf):
     for kind, kw, thr in configs:
         if kind == "window":
             fn = lambda: snx.snx_affine_normals(dn, cam, affine=aff, normals=nrm, **kw)
+        elif kind == "labels":
+            fn = lambda: snx.snx_affine_normals_labels(dn, lab, cam, affine=aff, normals=nrm, **kw)
         else:
             fn = lambda: snx.snx_affine_normals_star(dn, cam, affine=aff, normals=nrm, **kw)
         ms = timed(fn)
         fn()
         torch.cuda.synchronize()
         e_all, e_band, cov = errors()
-        row = {"support": "9x9 window" if kind == "window" else
+        name = {"window": "9x9 window", "labels": "9x9 window restricted to the component"}
+        row = {"support": name[kind] if kind in name else
                f"star 8 dirs x 10 steps, {'CD k' if kind == 'star_cd' else 'ST t'} = {thr}",
                "ms_per_frame": round(ms, 4), "mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
                "coverage": cov, "mean_err_deg": e_all, "mean_err_edge_band_deg": e_band}
@@ -466,7 +474,7 @@ def main():
     if batched:
         out.update(batched)
     if star:
-        out["star_fill"] = star
+        out["adaptive_support"] = star
     print(json.dumps(out), flush=True)
 
 
