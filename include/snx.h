@@ -231,6 +231,22 @@ snx_status snx_point_cloud(const float *disp_dn, int64_t disp_stride,
                            const snx_camera *cam, snx_point *out, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * snx_compact_points -- the compacted oriented point cloud: the records of
+ * `points` (width * height contiguous records, as written by snx_point_cloud,
+ * snx_oriented_point_cloud or snx_pipeline) whose flags hold
+ * SNX_POINT_DEFINED, copied unchanged and contiguously to `out` in raster
+ * order; *count (device int32) receives their number.  out must hold
+ * width * height records and must not overlap points.  workspace: device
+ * memory of at least snx_compact_points_workspace_size(width, height) bytes,
+ * owned by the caller, scratch after the call; concurrent calls need distinct
+ * workspaces.  width == 0 or height == 0 writes *count = 0.
+ * ------------------------------------------------------------------------- */
+size_t snx_compact_points_workspace_size(int32_t width, int32_t height);
+snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t height,
+                              snx_point *out, int32_t *count,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * snx_oriented_point_cloud -- filter, gradients, A, normal and point records in
  * ONE kernel, given component labels already computed by snx_components on the
  * same raw disparity.  Outputs are bit-identical to snx_denoise ->

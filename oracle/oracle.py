@@ -12,6 +12,7 @@ Stage functions (the C file cites the paper's passage for each):
   components(D, k, t)       min-index labels of covered-depth components
   point_cloud(Dt, n, cam)   back-projected points with normals
   affine_labels(Dt, lab, ng) a1, a2 over the window restricted to the centre's component
+  compact_points(rec)       the defined records of a dense cloud in raster order
   star_mask(Dt, u, v, ...)  star-fill support of one pixel (adaptive region)
   star_affine(Dt, ...)      a1, a2 and definedness over the star-fill support
   pipeline(D, cam, ...)     all of the above, in order
@@ -140,6 +141,18 @@ def affine_labels(Dt, lab, ng: int, min_support: int | None = None):
                                  ms, a1, a2, d) != 0:
         raise ValueError("oracle affine_labels: bad arguments")
     return a1, a2, d.astype(bool)
+
+
+POINT_DEFINED = 1
+
+
+def compact_points(records):
+    """The compacted oriented point cloud: the records whose flags hold the
+    defined bit, in raster order.  records: [H, W, 8] float32 (x, y, z, nx, ny,
+    nz, label bits, flag bits); returns [n, 8] float32."""
+    r = np.ascontiguousarray(records, dtype=np.float32).reshape(-1, 8)
+    flags = r[:, 7].view(np.uint32)
+    return r[(flags & POINT_DEFINED) != 0]
 
 
 STOP_CD, STOP_ST = 0, 1

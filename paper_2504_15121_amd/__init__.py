@@ -5,7 +5,7 @@ The computation lives in hand-written HIP kernels for gfx950 behind the C ABI of
 tensors into those calls.  Entry points (same names as the C functions):
 
     snx_denoise, snx_affine_normals, snx_affine_normals_labels, snx_affine_normals_star, snx_components,
-    snx_point_cloud,
+    snx_point_cloud, snx_compact_points,
     snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part, snx_components_workspace_size,
     snx_pipeline_workspace_size
 """
@@ -13,6 +13,7 @@ from ._lib import (snx_autotune, snx_tune_set, snx_cnn_param_count, snx_cnn_pack
                    snx_cnn_workspace_size, snx_cnn_pack, snx_cnn_denoise, snx_cnn_train_step,
                    cnn_model, Plan, FILTER_LSQ, FILTER_CNN, POINT_DEFINED, POINT_LABELLED, SnxError, load, snx_affine_normals,
                    snx_affine_normals_labels, snx_affine_normals_star, STOP_CD, STOP_ST,
+                   snx_compact_points, snx_compact_points_workspace_size,
                    snx_components, snx_components_workspace_size, snx_denoise,
                    snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part,
                    snx_pipeline_workspace_size, snx_point_cloud, PART_FOREST, PART_POINTS)
@@ -20,6 +21,7 @@ from ._lib import (snx_autotune, snx_tune_set, snx_cnn_param_count, snx_cnn_pack
 __all__ = ["load", "snx_autotune", "snx_tune_set", "snx_cnn_param_count",
            "snx_cnn_packed_bytes", "snx_cnn_workspace_size", "snx_cnn_pack", "snx_cnn_denoise",
            "snx_cnn_train_step", "cnn_model", "Plan", "FILTER_LSQ", "FILTER_CNN", "SnxError", "POINT_DEFINED", "POINT_LABELLED", "snx_denoise",
-           "snx_affine_normals", "snx_affine_normals_labels", "snx_affine_normals_star", "STOP_CD", "STOP_ST", "snx_components", "snx_components_workspace_size",
+           "snx_affine_normals", "snx_affine_normals_labels", "snx_affine_normals_star",
+           "snx_compact_points", "snx_compact_points_workspace_size", "STOP_CD", "STOP_ST", "snx_components", "snx_components_workspace_size",
            "snx_point_cloud", "snx_oriented_point_cloud", "snx_pipeline", "snx_pipeline_part",
            "snx_pipeline_workspace_size"]

@@ -74,6 +74,8 @@ SIGNATURES = {
     "snx_denoise": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_denoise_params), _P]),
     "snx_affine_normals": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                   C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
+    "snx_compact_points_workspace_size": (_SZ, [_I32, _I32]),
+    "snx_compact_points": (_I32, [_P, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "snx_affine_normals_labels": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                          C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
     "snx_affine_normals_star": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
@@ -212,6 +214,32 @@ def snx_affine_normals(disp_dn, cam, affine=None, normals=None, window=9, min_su
     c = camera(cam)
     _check(load().snx_affine_normals(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
                                      _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
+
+
+def snx_compact_points_workspace_size(width, height):
+    return int(load().snx_compact_points_workspace_size(width, height))
+
+
+def snx_compact_points(points, out, count, workspace, stream=None):
+    """Defined records of `points` ([H, W, 8] float32 records, contiguous)
+    packed into `out` (at least H*W records, contiguous) in raster order; the
+    number goes to `count` (int32 device tensor)."""
+    import torch
+    if points.dim() != 3 or points.shape[2] != 8 or points.dtype != torch.float32:
+        raise ValueError("points must be [H, W, 8] float32 records")
+    if not points.is_contiguous() or not out.is_contiguous():
+        raise ValueError("points and out must be contiguous")
+    H, W = points.shape[0], points.shape[1]
+    if out.dtype != torch.float32 or out.numel() < H * W * 8:
+        raise ValueError("out must be float32 with room for H*W records")
+    if count.dtype != torch.int32 or count.numel() < 1:
+        raise ValueError("count must be an int32 tensor")
+    for t in (points, out, count, workspace):
+        if t.device.type != "cuda":
+            raise ValueError("tensors must be on the GPU")
+    _check(load().snx_compact_points(_ptr(points), W, H, _ptr(out), _ptr(count), _ptr(workspace),
+                                     workspace.numel() * workspace.element_size(),
+                                     _stream(stream)))
 
 
 def snx_affine_normals_labels(disp_dn, labels, cam, affine=None, normals=None, window=9,

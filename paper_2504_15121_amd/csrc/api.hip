@@ -195,6 +195,42 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride, int32_t widt
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_affine_normals");
 }
 
+static size_t ws_compact(int32_t w, int32_t h)
+{
+    if (!size_ok(w, h)) return 0;
+    return 256 + 2 * sizeof(int32_t) * (size_t)snx::compact_chunks((int64_t)w * h);
+}
+
+size_t snx_compact_points_workspace_size(int32_t width, int32_t height)
+{
+    return ws_compact(width, height);
+}
+
+snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t height,
+                              snx_point *out, int32_t *count, void *workspace,
+                              size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (!count) return fail(SNX_ERR_ARG, "count is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (width == 0 || height == 0) {
+        hipError_t e = snx::launch_fill_i32(count, 0, 1, s);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points");
+    }
+    if (!points || !out) return fail(SNX_ERR_ARG, "points or out is NULL");
+    const int64_t n = (int64_t)width * height;
+    const char *pb = reinterpret_cast<const char *>(points), *ob = reinterpret_cast<const char *>(out);
+    const int64_t bytes = n * (int64_t)sizeof(snx_point);
+    if (pb < ob + bytes && ob < pb + bytes) return fail(SNX_ERR_ARG, "out overlaps points");
+    if (!workspace || workspace_bytes < ws_compact(width, height))
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_compact(width, height));
+    int32_t *cc = reinterpret_cast<int32_t *>(static_cast<char *>(workspace) + 256);
+    int32_t *co = cc + snx::compact_chunks(n);
+    hipError_t e = snx::launch_compact(points, n, out, count, cc, co, s);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points");
+}
+
 snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride, const int32_t *labels,
                                      int64_t label_stride, int32_t width, int32_t height,
                                      const snx_camera *cam, const snx_normal_params *params,

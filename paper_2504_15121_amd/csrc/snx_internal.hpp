@@ -48,6 +48,11 @@ bool set_tile_height(int rf, int rg, int W, int H, int th);
 hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H, hipStream_t s,
                             int *chosen);
 
+// Compacted point cloud (compact.hip): the defined records in raster order.
+int64_t compact_chunks(int64_t n);
+hipError_t launch_compact(const snx_point *in, int64_t n, snx_point *out, int32_t *count,
+                          int32_t *chunk_count, int32_t *chunk_off, hipStream_t s);
+
 // Component-restricted gradient window (restricted.hip): the n_g window keeps
 // only the valid pixels whose label equals the centre's.
 struct RestrictArgs {

@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 25
+    assert len(names) == 27
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -97,6 +97,18 @@ def test_affine_normals_validation(lib):
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, C.byref(cam), C.byref(ok),
                                   FAKE, FAKE, 32, None) == 1
     assert lib.snx_affine_normals(FAKE, 64, 64, 8, None, C.byref(ok), FAKE, FAKE, 64, None) == 1
+
+
+def test_compact_validation(lib):
+    cnt = FAKE
+    assert lib.snx_compact_points_workspace_size(1920, 1080) == 256 + 8 * ((1920 * 1080 + 4095) // 4096)
+    ws = lib.snx_compact_points_workspace_size(64, 64)
+    assert lib.snx_compact_points(FAKE, 64, 64, FAKE, None, FAKE, ws, None) == 1       # no count
+    assert lib.snx_compact_points(None, 64, 64, FAKE, cnt, FAKE, ws, None) == 1
+    assert lib.snx_compact_points(FAKE, 64, 64, FAKE, cnt, FAKE, ws, None) == 1        # overlap
+    assert lib.snx_compact_points(FAKE, 64, 64, C.c_void_p(0x10000000), cnt, FAKE, ws - 1,
+                                  None) == 3
+    assert lib.snx_compact_points(FAKE, -1, 64, FAKE, cnt, FAKE, ws, None) == 1
 
 
 def test_labels_validation(lib):
