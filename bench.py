@@ -23,6 +23,9 @@ replay of a captured batch plan (snx_plan_run) per step:
                    sigma = 0.75 px, 10 % invalid): the learned filter batched,
                    and the plain filter batched, with the mean angular error of
                    each against the generator's normals on the distinct frames
+  compact_points   the headline step's dense records compacted to the defined
+                   points in raster order (snx_compact_points): time, count and
+                   algorithmic GB/s (records read once, defined records written)
   adaptive_support the headline frame's filtered disparity through the square
                    9x9 window, the 9x9 window restricted to the centre's surface
                    component, and the adaptive star-fill support (8 directions,
@@ -265,6 +268,28 @@ def iso_sweep(args):
                   f"{ms:.4f} | {W * H / (ms * 1e-3) / 1e6:.0f} |", flush=True)
 
 
+def bench_compact(snx, torch, dev, s, W, H):
+    """Compaction of one step's dense records (already in HBM)."""
+    out = torch.empty((W * H, 8), device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(snx.snx_compact_points_workspace_size(W, H), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        snx.snx_compact_points(s["pts"], out, cnt, ws)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(20):
+        snx.snx_compact_points(s["pts"], out, cnt, ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / 20
+    n = int(cnt.item())
+    gbs = (W * H * 32 + n * 32) / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "defined": n, "of": W * H,
+            "algorithmic_GBps": round(gbs, 1), "frac_of_8TBps": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def bench_star(snx, torch, np, dev, sc, cam, nf):
     """Square window, component-restricted window and star-fill support on the
     headline frame (same D~)."""
@@ -438,6 +463,7 @@ def main():
 
     batched = None if args.no_batched else bench_batched(args, snx, torch, np, dev, nf, ng)
     star = None if args.no_star else bench_star(snx, torch, np, dev, sc, cam, nf)
+    compact = bench_compact(snx, torch, dev, sets[0], W, H)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -470,6 +496,7 @@ def main():
         "mean_angular_error_deg": round(mean_err, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "compact_points": compact,
     }
     if batched:
         out.update(batched)
