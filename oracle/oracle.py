@@ -10,6 +10,7 @@ Stage functions (the C file cites the paper's passage for each):
   affine(Dt, ng)            a1, a2 and definedness (anchored masked LSQ)
   normals(Dt, a1, a2, ...)  normal from the constraint-vector cross product
   components(D, k, t)       min-index labels of covered-depth components
+  components_crease(D, n, ...) the same with a normal-crease test on every edge
   point_cloud(Dt, n, cam)   back-projected points with normals
   affine_labels(Dt, lab, ng) a1, a2 over the window restricted to the centre's component
   compact_points(rec)       the defined records of a dense cloud in raster order
@@ -50,6 +51,8 @@ def load():
                                     C.POINTER(C.c_int64)]
     lib.snxo_point_cloud.argtypes = [_dp, _dp, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
     lib.snxo_num_threads.argtypes = []
+    lib.snxo_components_crease.argtypes = [_fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
+                                           C.c_double, _i32, C.POINTER(C.c_int64)]
     lib.snxo_affine_labels.argtypes = [_dp, _i32, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp,
                                        _u8]
     lib.snxo_star_mask.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
@@ -58,7 +61,7 @@ def load():
                                      C.c_double, C.c_double, C.c_int, _dp, _dp, _u8]
     for f in ("snxo_denoise", "snxo_affine", "snxo_normals", "snxo_components",
               "snxo_point_cloud", "snxo_num_threads", "snxo_star_mask", "snxo_star_affine",
-              "snxo_affine_labels"):
+              "snxo_affine_labels", "snxo_components_crease"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -126,6 +129,20 @@ def point_cloud(Dt, nrm, cam) -> np.ndarray:
     load().snxo_point_cloud(Dt, _as_f64(nrm), W, H, cam.fx, cam.fy,
                             cam.baseline, cam.u0, cam.v0, out)
     return out
+
+
+def components_crease(D, nrm, k_rel: float = 0.1, t_abs: float = 1.0, cos_min: float = 0.9):
+    """Labels and count of the components whose edges pass both the covered-depth
+    predicate and n_p . n_q >= cos_min (nrm: float32 [3, H, W]; NaN = undefined)."""
+    D = np.ascontiguousarray(D, dtype=np.float32)
+    H, W = D.shape
+    n = np.ascontiguousarray(nrm, dtype=np.float32).reshape(3, H, W)
+    lab = np.empty((H, W), np.int32)
+    cnt = C.c_int64(0)
+    if load().snxo_components_crease(D, n, W, H, C.c_float(k_rel), C.c_float(t_abs),
+                                     float(cos_min), lab, C.byref(cnt)) != 0:
+        raise MemoryError("oracle components_crease")
+    return lab, int(cnt.value)
 
 
 def affine_labels(Dt, lab, ng: int, min_support: int | None = None):

@@ -29,6 +29,9 @@
  *                       predicate (Sec. 3.4, CD), labels = minimum linear index,
  *                       breadth-first flood fill in raster order
  *   snxo_point_cloud    X from the rectified projections of Sec. 2 plus n
+ *   snxo_components_crease  components whose 4-neighbour edges must also pass a
+ *                       normal-crease test (depth-continuous creases, which the
+ *                       covered-depth rule misses by Sec. 3.4's own account)
  *   snxo_affine_labels  a1, a2 with the n_g window restricted to the centre's
  *                       surface component (Sec. 3.4's concern about neighbouring
  *                       surfaces, with the components of snxo_components)
@@ -315,6 +318,58 @@ int snxo_components(const float *D, int W, int H, float k_rel, float t_abs,
                 const int64_t q = nb[k];
                 if (q < 0 || labels[q] != -1) continue;
                 if (!joined(D[p], D[q], k_rel, t_abs)) continue;
+                labels[q] = (int32_t)s;
+                queue[tail++] = q;
+            }
+        }
+    }
+    free(queue);
+    *num_components = count;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Crease-aware components: as snxo_components, and an edge also needs the   */
+/* two pixels' unit normals (float32 planes nrm[0..2][v * W + u]) to agree:   */
+/*   n_p . n_q = ((nx_p nx_q + ny_p ny_q) + nz_p nz_q) >= cos_min             */
+/* in binary64 (each product of two float32 values is exact); a pixel whose  */
+/* normal is undefined (NaN) imposes no crease test.  Sec. 3.4 notes that    */
+/* covered depth misses depth-continuous (C0) edges; this is the test that   */
+/* separates surfaces meeting at such a crease.                              */
+/* ------------------------------------------------------------------------ */
+static int crease_ok(const float *nrm, int64_t plane, int64_t p, int64_t q, double cmin)
+{
+    const double ax = nrm[p], ay = nrm[plane + p], az = nrm[2 * plane + p];
+    const double bx = nrm[q], by = nrm[plane + q], bz = nrm[2 * plane + q];
+    if (isnan(ax) || isnan(bx)) return 1;
+    return ((ax * bx + ay * by) + az * bz) >= cmin;
+}
+
+int snxo_components_crease(const float *D, const float *nrm, int W, int H, float k_rel,
+                           float t_abs, double cos_min, int32_t *labels,
+                           int64_t *num_components)
+{
+    const int64_t N = (int64_t)W * H;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    if (!queue) return 2;
+    for (int64_t i = 0; i < N; ++i) labels[i] = -1;
+    int64_t count = 0;
+    for (int64_t s = 0; s < N; ++s) {
+        if (labels[s] != -1 || !is_valid((double)D[s])) continue;
+        ++count;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        labels[s] = (int32_t)s;
+        while (head < tail) {
+            const int64_t p = queue[head++];
+            const int u = (int)(p % W), v = (int)(p / W);
+            const int64_t nb[4] = {u > 0 ? p - 1 : -1, u + 1 < W ? p + 1 : -1,
+                                   v > 0 ? p - W : -1, v + 1 < H ? p + W : -1};
+            for (int k = 0; k < 4; ++k) {
+                const int64_t q = nb[k];
+                if (q < 0 || labels[q] != -1) continue;
+                if (!joined(D[p], D[q], k_rel, t_abs)) continue;
+                if (!crease_ok(nrm, N, p, q, cos_min)) continue;
                 labels[q] = (int32_t)s;
                 queue[tail++] = q;
             }
