@@ -216,6 +216,26 @@ snx_status snx_components(const float *disp_raw, int64_t stride,
                           void *stream);
 
 /* ---------------------------------------------------------------------------
+ * snx_components_creases -- snx_components where every 4-neighbour edge must
+ * also pass a normal-crease test: n_p . n_q = ((nx_p nx_q + ny_p ny_q) +
+ * nz_p nz_q) >= crease_cos in binary64 on the float32 normals (a pixel whose
+ * normal is NaN imposes no test).  Covered depth alone joins surfaces that
+ * meet at a depth-continuous crease (Sec. 3.4 says so); this test separates
+ * them.  normals: 3 planes [height x normals_stride] (nx, ny, nz, as written
+ * by snx_affine_normals), the second starting at normals + height *
+ * normals_stride.  crease_cos in [-1, 1].  Labels, count, workspace and
+ * errors as in snx_components.
+ * ------------------------------------------------------------------------- */
+snx_status snx_components_creases(const float *disp_raw, int64_t stride,
+                                  const float *normals, int64_t normals_stride,
+                                  int32_t width, int32_t height,
+                                  const snx_component_params *params, double crease_cos,
+                                  int32_t *labels, int64_t label_stride,
+                                  int32_t *num_components,
+                                  void *workspace, size_t workspace_bytes,
+                                  void *stream);
+
+/* ---------------------------------------------------------------------------
  * snx_point_cloud -- dense oriented point cloud (abstract; Sec. 2 projections).
  * Where the normal is defined: z = f_x b / D, x = (u - u0) z / f_x,
  * y = (v - v0) z / f_y with D the denoised disparity, plus the normal; elsewhere

@@ -74,6 +74,9 @@ SIGNATURES = {
     "snx_denoise": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_denoise_params), _P]),
     "snx_affine_normals": (_I32, [_P, _I64, _I32, _I32, C.POINTER(snx_camera),
                                   C.POINTER(snx_normal_params), _P, _P, _I64, _P]),
+    "snx_components_creases": (_I32, [_P, _I64, _P, _I64, _I32, _I32,
+                                      C.POINTER(snx_component_params), C.c_double, _P, _I64, _P,
+                                      _P, _SZ, _P]),
     "snx_compact_points_workspace_size": (_SZ, [_I32, _I32]),
     "snx_compact_points": (_I32, [_P, _I32, _I32, _P, _P, _P, _SZ, _P]),
     "snx_affine_normals_labels": (_I32, [_P, _I64, _P, _I64, _I32, _I32, C.POINTER(snx_camera),
@@ -214,6 +217,22 @@ def snx_affine_normals(disp_dn, cam, affine=None, normals=None, window=9, min_su
     c = camera(cam)
     _check(load().snx_affine_normals(_ptr(disp_dn), ld, W, H, C.byref(c), C.byref(p),
                                      _ptr(affine), _ptr(normals), out_ld, _stream(stream)))
+
+
+def snx_components_creases(disp, normals, labels, workspace, num_components=None, k_rel=0.1,
+                           t_abs=1.0, crease_cos=0.9, stream=None):
+    """Components whose edges pass covered depth and n_p . n_q >= crease_cos."""
+    import torch
+    H, W = disp.shape
+    ln = _planes(normals, 3, H, W, "normals")
+    p = snx_component_params(k_rel, t_abs)
+    _check(load().snx_components_creases(_ptr(disp), _img(disp, torch.float32, "disp"),
+                                         _ptr(normals), ln if ln is not None else W, W, H,
+                                         C.byref(p), float(crease_cos), _ptr(labels),
+                                         _img(labels, torch.int32, "labels"), _ptr(num_components),
+                                         _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream)))
 
 
 def snx_compact_points_workspace_size(width, height):

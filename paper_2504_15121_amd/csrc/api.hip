@@ -319,7 +319,9 @@ size_t snx_components_workspace_size(int32_t width, int32_t height) { return ws_
 static snx_status components_impl(const float *disp, int64_t stride, int32_t width, int32_t height,
                                   const snx_component_params *p, int32_t *labels,
                                   int64_t label_stride, int32_t *num_components, void *workspace,
-                                  size_t workspace_bytes, hipStream_t s, const char *who)
+                                  size_t workspace_bytes, hipStream_t s, const char *who,
+                                  const float *nrm = nullptr, int64_t nrm_stride = 0,
+                                  double crease_cos = 0.0)
 {
     snx::CclArgs c;
     c.D = disp;
@@ -333,6 +335,10 @@ static snx_status components_impl(const float *disp, int64_t stride, int32_t wid
     c.parent = label_stride == width ? labels : reinterpret_cast<int32_t *>(
                                                     static_cast<char *>(workspace) + 256);
     c.count = num_components;
+    c.nrm = nrm;
+    c.ld_nrm = nrm_stride;
+    c.plane_nrm = nrm_stride * (int64_t)height;
+    c.crease_cos = crease_cos;
     (void)workspace_bytes;
     hipError_t e = snx::launch_components(c, s);
     return e == hipSuccess ? SNX_OK : hip_fail(e, who);
@@ -359,6 +365,33 @@ snx_status snx_components(const float *disp_raw, int64_t stride, int32_t width, 
     return components_impl(disp_raw, stride, width, height, params, labels, label_stride,
                            num_components, workspace, workspace_bytes, (hipStream_t)stream,
                            "snx_components");
+}
+
+snx_status snx_components_creases(const float *disp_raw, int64_t stride, const float *normals,
+                                  int64_t normals_stride, int32_t width, int32_t height,
+                                  const snx_component_params *params, double crease_cos,
+                                  int32_t *labels, int64_t label_stride, int32_t *num_components,
+                                  void *workspace, size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    snx_status st = check_comp(params);
+    if (st) return st;
+    if (!std::isfinite(crease_cos) || crease_cos < -1.0 || crease_cos > 1.0)
+        return fail(SNX_ERR_ARG, "crease_cos must be in [-1, 1]");
+    if (width == 0 || height == 0) {
+        if (!num_components) return SNX_OK;
+        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, (hipStream_t)stream);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_components_creases");
+    }
+    if ((st = check_image(disp_raw, stride, width, "disp_raw"))) return st;
+    if ((st = check_image(normals, normals_stride, width, "normals"))) return st;
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    if (!workspace || workspace_bytes < ws_components(width, height))
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_components(width, height));
+    return components_impl(disp_raw, stride, width, height, params, labels, label_stride,
+                           num_components, workspace, workspace_bytes, (hipStream_t)stream,
+                           "snx_components_creases", normals, normals_stride, crease_cos);
 }
 
 snx_status snx_point_cloud(const float *disp_dn, int64_t disp_stride, const float *normals,

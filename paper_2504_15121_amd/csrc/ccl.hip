@@ -70,19 +70,22 @@ __device__ __forceinline__ void g_union(int32_t *par, int a, int b)
     }
 }
 
-template <int RF>
+template <int RF, bool CREASE = false>
 struct FrontSmem {
     static constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
     float sIn[inH * inW];
     int par[kCH * kCW];
     unsigned long long hmask[kCH];
+    float nrm[CREASE ? 3 * kCH * kCW : 1];    // crease-aware: the tile's normals
 };
 
-// One 64 x 32 tile: filter (window 1 or 3) and local component forest.
-template <int RF>
-__device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by, FrontSmem<RF> &sm)
+// One 64 x 32 tile: filter (window 1 or 3) and local component forest
+// (crease-aware with CREASE: every edge also passes crease_ok).
+template <int RF, bool CREASE = false>
+__device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
+                                           FrontSmem<RF, CREASE> &sm)
 {
-    constexpr int inW = FrontSmem<RF>::inW, inH = FrontSmem<RF>::inH;
+    constexpr int inW = FrontSmem<RF, CREASE>::inW, inH = FrontSmem<RF, CREASE>::inH;
     float *sIn = sm.sIn;
     int *par = sm.par;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -105,6 +108,15 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by, F
         const int e = threadIdx.x + k * kFrontWaves * 64;
         if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
     }
+    if (CREASE) {
+        for (int e = threadIdx.x; e < 3 * kCH * kCW; e += kFrontWaves * 64) {
+            const int c = e / (kCH * kCW), l = e - c * (kCH * kCW);
+            const int gy = y0 + (l >> 6), gxx = x0 + (l & 63);
+            float n = __builtin_nanf("");
+            if (gy < a.H && gxx < a.W) n = a.nrm[c * a.plane_nrm + (int64_t)gy * a.ld_nrm + gxx];
+            sm.nrm[e] = n;
+        }
+    }
     __syncthreads();
 
     const int gx = x0 + lane;
@@ -119,8 +131,20 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by, F
         }
     }
 
-    local_forest([&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; }, par, sm.hmask,
-                 lane, wave, kFrontWaves, a.k_rel, a.t_abs);
+    auto val = [&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; };
+    if (CREASE) {
+        const float *n = sm.nrm;
+        constexpr int P = kCH * kCW;
+        local_forest(val, par, sm.hmask, lane, wave, kFrontWaves, a.k_rel, a.t_abs,
+                     [&](int la, int xa, int lb, int xb) {
+                         const int i = la * kCW + xa, j = lb * kCW + xb;
+                         return crease_ok(n[i], n[P + i], n[2 * P + i], n[j], n[P + j], n[2 * P + j],
+                                          a.crease_cos);
+                     });
+    } else {
+        local_forest(val, par, sm.hmask, lane, wave, kFrontWaves, a.k_rel, a.t_abs,
+                     [](int, int, int, int) { return true; });
+    }
 
     for (int ly = wave; ly < kCH; ly += kFrontWaves) {
         const int gy = y0 + ly;
@@ -135,13 +159,13 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by, F
     }
 }
 
-template <int RF>
+template <int RF, bool CREASE>
 __global__ void __launch_bounds__(kFrontWaves * 64)
 k_front(FrontArgs a)
 {
-    __shared__ FrontSmem<RF> sm;
+    __shared__ FrontSmem<RF, CREASE> sm;
     if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
-    front_tile<RF>(a, blockIdx.x, blockIdx.y, sm);
+    front_tile<RF, CREASE>(a, blockIdx.x, blockIdx.y, sm);
 }
 
 // Persistent front over the (frame, tile) work list of a batch: workgroups
@@ -180,9 +204,21 @@ k_front_batch(const BatchFrame *frames, const int *tile_off, const int *tile_fra
 // column x.  Pair i is implied by pair i-1 along the same seam when pair i-1 is
 // joined and each side of pair i is joined to its side of pair i-1 (those edges
 // lie inside one tile and were united by the front kernel).
+// nrm (crease-aware components; else NULL): the normal planes, and every
+// seam pair also passes crease_ok (the implied-pair shortcut is not taken).
+__device__ __forceinline__ bool seam_crease(const float *nrm, int64_t ld_nrm, int64_t plane,
+                                            double ccos, int yp, int xp, int yq, int xq)
+{
+    const int64_t i = (int64_t)yp * ld_nrm + xp, j = (int64_t)yq * ld_nrm + xq;
+    return crease_ok(nrm[i], nrm[plane + i], nrm[2 * plane + i], nrm[j], nrm[plane + j],
+                     nrm[2 * plane + j], ccos);
+}
+
 __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, int H, double k_rel,
                                            double t_abs, int32_t *par, int n_vseams,
-                                           int n_hseams, int64_t i)
+                                           int n_hseams, int64_t i, const float *nrm = nullptr,
+                                           int64_t ld_nrm = 0, int64_t plane_nrm = 0,
+                                           double ccos = 0.0)
 {
     const int64_t nv = (int64_t)n_vseams * H;
     int p, q;
@@ -192,7 +228,9 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
         const float *r = D + (int64_t)y * ld;
         const float dp = r[x - 1], dq = r[x];
         if (!edge(dp, dq, k_rel, t_abs)) return;
-        if (y % kCH != 0) {
+        if (nrm) {
+            if (!seam_crease(nrm, ld_nrm, plane_nrm, ccos, y, x - 1, y, x)) return;
+        } else if (y % kCH != 0) {
             const float *u = r - ld;
             const float up = u[x - 1], uq = u[x];
             if (edge(up, uq, k_rel, t_abs) && edge(up, dp, k_rel, t_abs) &&
@@ -210,7 +248,9 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
         const float *rb = ra + ld;
         const float dp = ra[x], dq = rb[x];
         if (!edge(dp, dq, k_rel, t_abs)) return;
-        if (x % kCW != 0) {
+        if (nrm) {
+            if (!seam_crease(nrm, ld_nrm, plane_nrm, ccos, y - 1, x, y, x)) return;
+        } else if (x % kCW != 0) {
             const float lp = ra[x - 1], lq = rb[x - 1];
             if (edge(lp, lq, k_rel, t_abs) && edge(lp, dp, k_rel, t_abs) &&
                 edge(lq, dq, k_rel, t_abs))
@@ -224,10 +264,12 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
 
 __global__ void __launch_bounds__(256)
 k_ccl_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs, int32_t *par,
-            int n_vseams, int n_hseams)
+            int n_vseams, int n_hseams, const float *nrm, int64_t ld_nrm, int64_t plane_nrm,
+            double ccos)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    merge_pair(D, ld, W, H, k_rel, t_abs, par, n_vseams, n_hseams, i);
+    merge_pair(D, ld, W, H, k_rel, t_abs, par, n_vseams, n_hseams, i, nrm, ld_nrm, plane_nrm,
+               ccos);
 }
 
 // Seam pairs of every frame of a batch, one thread each.
@@ -302,12 +344,16 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s)
 hipError_t launch_front(const FrontArgs &a, hipStream_t s)
 {
     const dim3 grid((a.W + kCW - 1) / kCW, (a.H + kCH - 1) / kCH);
-    if (a.rf == 0)
-        hipLaunchKernelGGL(k_front<0>, grid, dim3(kFrontWaves * 64), 0, s, a);
-    else if (a.rf == 1)
-        hipLaunchKernelGGL(k_front<1>, grid, dim3(kFrontWaves * 64), 0, s, a);
-    else
+    if (a.nrm) {
+        if (a.rf != 0 || a.dn) return hipErrorInvalidValue;   // crease-aware: forest only
+        hipLaunchKernelGGL((k_front<0, true>), grid, dim3(kFrontWaves * 64), 0, s, a);
+    } else if (a.rf == 0) {
+        hipLaunchKernelGGL((k_front<0, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
+    } else if (a.rf == 1) {
+        hipLaunchKernelGGL((k_front<1, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -352,14 +398,15 @@ hipError_t launch_batch_reset(int *counters, int n_counters, const BatchFrame *f
 }
 
 hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
-                        int32_t *forest, hipStream_t s)
+                        int32_t *forest, hipStream_t s, const float *nrm, int64_t ld_nrm,
+                        int64_t plane_nrm, double crease_cos)
 {
     const int tx = (W + kCW - 1) / kCW, ty = (H + kCH - 1) / kCH;
     const int nv = tx - 1, nh = ty - 1;
     const int64_t pairs = (int64_t)nv * H + (int64_t)nh * W;
     if (pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ccl_merge, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, D, ld,
-                       W, H, k_rel, t_abs, forest, nv, nh);
+                       W, H, k_rel, t_abs, forest, nv, nh, nrm, ld_nrm, plane_nrm, crease_cos);
     return hipGetLastError();
 }
 
@@ -378,9 +425,14 @@ hipError_t launch_components(const CclArgs &a, hipStream_t s)
     f.ld_dn = 0;
     f.forest = a.parent;
     f.count = a.count;
+    f.nrm = a.nrm;
+    f.ld_nrm = a.ld_nrm;
+    f.plane_nrm = a.plane_nrm;
+    f.crease_cos = a.crease_cos;
     hipError_t e = launch_front(f, s);
     if (e != hipSuccess) return e;
-    e = launch_merge(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.parent, s);
+    e = launch_merge(a.D, a.ld, a.W, a.H, a.k_rel, a.t_abs, a.parent, s, a.nrm, a.ld_nrm,
+                     a.plane_nrm, a.crease_cos);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ccl_flatten, dim3((a.W + 63) / 64, (a.H + 3) / 4), dim3(256), 0, s, a);
     return hipGetLastError();

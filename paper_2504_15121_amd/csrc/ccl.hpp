@@ -30,6 +30,18 @@ __device__ __forceinline__ bool edge(float p, float q, double k_rel, double t_ab
     return valid_disp(p) && valid_disp(q) && joined(p, q, k_rel, t_abs);
 }
 
+// Normal-crease test of crease-aware components: the two unit normals agree,
+// ((ax bx + ay by) + az bz) >= cos_min in binary64 (each product of two float32
+// values is exact); an undefined (NaN) normal imposes no test.
+__device__ __forceinline__ bool crease_ok(float ax, float ay, float az, float bx, float by,
+                                          float bz, double cos_min)
+{
+#pragma clang fp contract(off)
+    if (ax != ax || bx != bx) return true;
+    const double d = ((double)ax * (double)bx + (double)ay * (double)by) + (double)az * (double)bz;
+    return d >= cos_min;
+}
+
 __device__ __forceinline__ int lds_find(const int *par, int x)
 {
     int p = par[x];
@@ -78,17 +90,20 @@ __device__ __forceinline__ int run_start(unsigned long long starts, int lane)
 // nwaves-th row.  Horizontal edges come from a 64-bit ballot and give the row
 // runs (first pixel = initial root); vertical edges are united with atomicMin
 // hooking except where the edge at lane-1 already joins the same two runs.
+// extra(ly_a, x_a, ly_b, x_b) is a further condition on an edge (always true for
+// the covered-depth components).
 // On return (after a barrier) par[] holds a local forest over ly*kCW + lane.
-template <class Val>
+template <class Val, class Extra>
 __device__ __forceinline__ void local_forest(Val val, int *par, unsigned long long *hmask,
                                              int lane, int wave, int nwaves, double k_rel,
-                                             double t_abs)
+                                             double t_abs, Extra extra)
 {
     for (int ly = wave; ly < kCH; ly += nwaves) {
         const float v = val(ly, lane);
         const float left = __shfl_up(v, 1);
         const bool ok = v > 0.0f;
-        const bool h = ok && lane > 0 && left > 0.0f && joined(v, left, k_rel, t_abs);
+        const bool h = ok && lane > 0 && left > 0.0f && joined(v, left, k_rel, t_abs) &&
+                       extra(ly, lane > 0 ? lane - 1 : lane, ly, lane);
         const unsigned long long hb = __ballot(h);
         const unsigned long long vb = __ballot(ok);
         par[ly * kCW + lane] = ok ? ly * kCW + run_start(vb & ~hb, lane) : -1;
@@ -98,7 +113,8 @@ __device__ __forceinline__ void local_forest(Val val, int *par, unsigned long lo
     for (int ly = 1 + wave; ly < kCH; ly += nwaves) {
         const float v = val(ly, lane);
         const float up = val(ly - 1, lane);
-        const bool e = v > 0.0f && up > 0.0f && joined(v, up, k_rel, t_abs);
+        const bool e = v > 0.0f && up > 0.0f && joined(v, up, k_rel, t_abs) &&
+                       extra(ly - 1, lane, ly, lane);
         const unsigned long long eb = __ballot(e);
         const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
         if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);

@@ -97,10 +97,14 @@ struct FrontArgs {
     int64_t ld_dn;
     int32_t *forest;       // W*H contiguous
     int32_t *count;        // nullable: zeroed here
+    const float *nrm = nullptr;   // crease-aware components: normal planes (else NULL)
+    int64_t ld_nrm = 0, plane_nrm = 0;
+    double crease_cos = 0.0;
 };
 hipError_t launch_front(const FrontArgs &a, hipStream_t s);
 hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
-                        int32_t *forest, hipStream_t s);
+                        int32_t *forest, hipStream_t s, const float *nrm = nullptr,
+                        int64_t ld_nrm = 0, int64_t plane_nrm = 0, double crease_cos = 0.0);
 
 // One frame of a batch plan: the arguments of its front (filter + forest, and
 // the seam merge) and back (gradients, normals, labels, records) stages.
@@ -130,6 +134,9 @@ struct CclArgs {
     int32_t *labels;       // output (may equal parent when ld_lab == W)
     int64_t ld_lab;
     int32_t *count;        // nullable
+    const float *nrm = nullptr;   // crease-aware components: normal planes (else NULL)
+    int64_t ld_nrm = 0, plane_nrm = 0;
+    double crease_cos = 0.0;
 };
 hipError_t launch_components(const CclArgs &a, hipStream_t s);
 
