@@ -28,7 +28,8 @@ replay of a captured batch plan (snx_plan_run) per step:
                    algorithmic GB/s (records read once, defined records written)
   adaptive_support the headline frame's filtered disparity through the square
                    9x9 window, the 9x9 window restricted to the centre's surface
-                   component, and the adaptive star-fill support (8 directions,
+                   component (covered-depth components, and crease-aware ones from
+                   first-pass normals), and the adaptive star-fill support (8 directions,
                    10 steps, covered-depth and depth-Laplacian stopping): time
                    per frame, coverage, mean angular error over all defined
                    pixels and over the band within 4 px of a surface boundary
@@ -337,7 +338,11 @@ def bench_star(snx, torch, np, dev, sc, cam, nf):
                 round(float(ok.sum() / max(valid.sum(), 1)), 4))
 
     rows = []
-    configs = [("window", dict(window=9), None), ("labels", dict(window=9), None)]
+    configs = [("window", dict(window=9), None), ("labels", dict(window=9), None),
+               ("crease", dict(window=9), 0.9)]
+    # crease-aware labels from the first-pass 9x9 normals
+    nrm9 = torch.empty((3, H, W), device=dev)
+    labc = torch.empty((H, W), dtype=torch.int32, device=dev)
     for thr in (0.05, 0.1, 0.2):
         configs.append(("star_cd", dict(directions=8, steps=10, stop=snx.STOP_CD, threshold=thr), thr))
     for thr in (0.5, 2.0):
@@ -347,13 +352,21 @@ def bench_star(snx, torch, np, dev, sc, cam, nf):
             fn = lambda: snx.snx_affine_normals(dn, cam, affine=aff, normals=nrm, **kw)
         elif kind == "labels":
             fn = lambda: snx.snx_affine_normals_labels(dn, lab, cam, affine=aff, normals=nrm, **kw)
+        elif kind == "crease":
+            def fn(kw=kw, thr=thr):
+                snx.snx_affine_normals(dn, cam, normals=nrm9, **kw)
+                snx.snx_components_creases(d, nrm9, labc, cws, k_rel=0.1, t_abs=1.0,
+                                           crease_cos=thr)
+                snx.snx_affine_normals_labels(dn, labc, cam, affine=aff, normals=nrm, **kw)
         else:
             fn = lambda: snx.snx_affine_normals_star(dn, cam, affine=aff, normals=nrm, **kw)
         ms = timed(fn)
         fn()
         torch.cuda.synchronize()
         e_all, e_band, cov = errors()
-        name = {"window": "9x9 window", "labels": "9x9 window restricted to the component"}
+        name = {"window": "9x9 window", "labels": "9x9 window restricted to the component",
+                "crease": "9x9 normals, crease-aware components (cos 0.9), then the 9x9 window "
+                          "restricted to them (all three calls)"}
         row = {"support": name[kind] if kind in name else
                f"star 8 dirs x 10 steps, {'CD k' if kind == 'star_cd' else 'ST t'} = {thr}",
                "ms_per_frame": round(ms, 4), "mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
