@@ -4,10 +4,14 @@ The computation lives in hand-written HIP kernels for gfx950 behind the C ABI of
 ``include/snx.h`` (``libsnx.so``); this package only marshals torch device
 tensors into those calls.  Entry points (same names as the C functions):
 
-    snx_denoise, snx_affine_normals, snx_affine_normals_labels, snx_affine_normals_star, snx_components,
-    snx_point_cloud, snx_compact_points,
-    snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part, snx_components_workspace_size,
-    snx_pipeline_workspace_size
+    snx_denoise, snx_affine_normals, snx_components, snx_point_cloud,
+    snx_oriented_point_cloud, snx_pipeline, snx_pipeline_part (+ workspace sizes),
+    snx_autotune, snx_tune_set;
+    the learned filter: snx_cnn_pack, snx_cnn_denoise, snx_cnn_train_step (+ sizes);
+    batch plans: Plan (snx_plan_create / run / destroy);
+    adaptive supports: snx_affine_normals_star (star fill), snx_affine_normals_labels
+    (window restricted to the centre's component), snx_components_creases;
+    snx_compact_points (the defined points in raster order).
 """
 from ._lib import (snx_autotune, snx_tune_set, snx_cnn_param_count, snx_cnn_packed_bytes,
                    snx_cnn_workspace_size, snx_cnn_pack, snx_cnn_denoise, snx_cnn_train_step,
