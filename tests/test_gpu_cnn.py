@@ -228,3 +228,48 @@ def test_learned_pipeline_equals_separate_calls():
     torch.cuda.synchronize()
     for a, b in ((dn, dn2), (nrm, nrm2), (lab, lab2), (pts, pts2)):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_forward_full_frame_sampled():
+    """The fused network on a full 2048x1024 road frame (the bench's inference
+    size) with the committed weights, checked at sampled pixels: an output
+    depends only on the disparity within 7 px (six 3x3 layers and the 3x3 mu),
+    so the oracle run on a 17x17 crop around a pixel (cut at the image border
+    where the pixel is near it) gives that pixel's exact reference."""
+    from oracle import cnn_oracle as cnn
+    from paper_2504_15121_amd import learned
+    snx = _snx()
+    print("case cnn forward full frame 2048x1024 sampled", flush=True)
+    flat = learned.load_checkpoint(learned.DEFAULT_MODEL)["params"].astype(np.float32)
+    p32, o = [], 0
+    for ci, co in cnn.LAYERS:
+        w = flat[o:o + co * ci * 9].astype(np.float64).reshape(co, ci, 3, 3)
+        o += co * ci * 9
+        b = flat[o:o + co].astype(np.float64)
+        o += co
+        p32.append((w, b))
+    assert o == flat.size
+    P, packed = _packed(snx, flat)
+    sc = scenes.road_scene(seed=5300)
+    H, W = sc.disp.shape
+    assert (W, H) == (2048, 1024)
+    ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=DEV)
+    out = torch.empty((H, W), device=DEV)
+    snx.snx_cnn_denoise(torch.from_numpy(sc.disp).to(DEV), snx.cnn_model(P, packed, ws), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    rng = np.random.default_rng(11)
+    pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (23, 24), (24, 23), (47, 48),
+           (H // 2, 24 * 40), (H // 2, 24 * 40 - 1), (H - 2, 1000), (5, W - 6)]
+    pts += [(int(v), int(u)) for v, u in zip(rng.integers(0, H, 37), rng.integers(0, W, 37))]
+    errs = []
+    for v, u in pts:
+        v0, v1, u0, u1 = max(0, v - 8), min(H, v + 9), max(0, u - 8), min(W, u + 9)
+        ref = cnn.forward(sc.disp[v0:v1, u0:u1].astype(np.float64), p32)[v - v0, u - u0]
+        if np.isnan(ref):
+            assert np.isnan(g[v, u]), (v, u)
+            continue
+        errs.append(abs(float(g[v, u]) - float(ref)))
+    errs = np.array(errs)
+    assert errs.size > 30
+    assert errs.max() <= 0.05 and errs.mean() <= 4e-3, (errs.max(), errs.mean())
