@@ -268,6 +268,48 @@ def iso_sweep(args):
             print(f"| {tag} | {'cnn' if cnn is not None else nf} | {ng} | {es / ec:.3f} | "
                   f"{ms:.4f} | {W * H / (ms * 1e-3) / 1e6:.0f} |", flush=True)
 
+    # the same frames with the star-fill support in place of the square window:
+    # filter (LSQ n_f or the network), then snx_affine_normals_star
+    dn = torch.empty((H, W), device=dev)
+    nrm = torch.empty((3, H, W), device=dev)
+
+    def run_star(k, nf, cnn, steps, thr):
+        if cnn is None:
+            snx.snx_denoise(d[k], dn, window=nf)
+        else:
+            snx.snx_cnn_denoise(d[k], cnn, dn)
+        snx.snx_affine_normals_star(dn, frames[k].cam, normals=nrm, directions=8, steps=steps,
+                                    stop=snx.STOP_CD, threshold=thr)
+
+    print()
+    print("| filter | star steps | CD k | mean angular error (deg) | ms per frame | Mpixel/s |")
+    print("|---|---|---|---|---|---|")
+    for steps in (10, 20, 32):
+        for thr in (0.02, 0.05):
+            for nf, cnn in ((3, None), (9, None), (3, model)):
+                es, ec = 0.0, 0
+                for k in range(len(frames)):
+                    run_star(k, nf, cnn, steps, thr)
+                    torch.cuda.synchronize()
+                    n = np.moveaxis(nrm.cpu().numpy(), 0, -1)
+                    e, c = angular_error_sum(np.concatenate([np.zeros_like(n), n], -1),
+                                             frames[k].normal)
+                    es, ec = es + e, ec + c
+                for _ in range(3):
+                    run_star(0, nf, cnn, steps, thr)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(10):
+                    run_star(0, nf, cnn, steps, thr)
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / 10
+                tag = "learned" if cnn is not None else f"LSQ n_f = {nf}"
+                print(f"| {tag} | {steps} | {thr} | {es / ec:.3f} | {ms:.4f} | "
+                      f"{W * H / (ms * 1e-3) / 1e6:.0f} |", flush=True)
+
 
 def bench_compact(snx, torch, dev, s, W, H):
     """Compaction of one step's dense records (already in HBM)."""
