@@ -89,13 +89,16 @@ k_star(StarArgs a)
             // in flight at once, and a stopped ray is carried as a predicate
             // (a stopped ray reads pixels still inside the tile and adds 0).
             const double dc64 = (double)Dc;
-            float lo[M], hi[M];
+            // range of the ray so far, as binary64 (exact images of the float
+            // values); once a ray has stopped its range is never read again,
+            // so it is updated without a select
+            double lo[M], hi[M];
             double wk[M];
             int nk[M], pp[M], pe[M];
             bool alive[M];
 #pragma unroll
             for (int mi = 0; mi < M; ++mi) {
-                lo[mi] = hi[mi] = Dc;
+                lo[mi] = hi[mi] = dc64;
                 wk[mi] = 0.0;
                 nk[mi] = 0;
                 pp[mi] = pc;
@@ -103,6 +106,7 @@ k_star(StarArgs a)
                 alive[mi] = true;
             }
             for (int k = 1; k <= s; ++k) {
+                const double kd = (double)k;
                 float vv[M];
 #pragma unroll
                 for (int mi = 0; mi < M; ++mi) {
@@ -114,19 +118,20 @@ k_star(StarArgs a)
 #pragma unroll
                 for (int mi = 0; mi < M; ++mi) {
                     const int m = mi * (8 / M);
-                    const float v = vv[mi];
-                    bool ok = alive[mi] && v > 0.0f;
+                    const double v = (double)vv[mi];
+                    bool ok = alive[mi] && v > 0.0;
                     if (STOP == kStopCD) {
-                        const float nlo = v < lo[mi] ? v : lo[mi], nhi = v > hi[mi] ? v : hi[mi];
-                        const double da = (double)nlo, db = (double)nhi;
+                        const double da = fmin(v, lo[mi]), db = fmax(v, hi[mi]);
                         ok = ok && !(dc64 * (db - da) > a.thr * (da * db));
-                        lo[mi] = ok ? nlo : lo[mi];
-                        hi[mi] = ok ? nhi : hi[mi];
+                        lo[mi] = da;
+                        hi[mi] = db;
                     } else {
                         pe[mi] += dir_y(m) * EW + dir_x(m);
                         ok = ok && !sE[pe[mi]];
                     }
-                    wk[mi] += ok ? (double)k * (double)v : 0.0;
+                    // k v is exact in binary64, so the fused form rounds as the
+                    // separate product and sum do
+                    wk[mi] = __builtin_fma(kd, ok ? v : 0.0, wk[mi]);
                     nk[mi] = ok ? k : nk[mi];
                     alive[mi] = ok;
                     any = any || ok;
