@@ -483,19 +483,28 @@ def main():
         step(sets[i % len(sets)])
     torch.cuda.synchronize()
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # the timed steps carry no per-step events: each event marker costs the
+    # GPU a few microseconds between kernels
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record()
     for i in range(args.steps):
-        step(sets[i % len(sets)], evs[i])
+        step(sets[i % len(sets)])
     t_end.record()
     torch.cuda.synchronize()
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / args.steps
-    comp_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    fused_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+
+    # split of a step into its two parts: further steps with event markers
+    # around each part (the markers' own cost included)
+    n_split = min(args.steps, 20)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n_split)]
+    for i in range(n_split):
+        step(sets[i % len(sets)], evs[i])
+    torch.cuda.synchronize()
+    comp_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / n_split
+    fused_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / n_split
     px = W * H
     value = px / (ms_per_step * 1e-3) / 1e6
 
@@ -508,13 +517,32 @@ def main():
     dt = np.abs((n[ok] * sc.normal[ok]).sum(-1))
     mean_err = float(np.degrees(np.arctan2(cr, dt)).mean())
 
-    achieved = FUSED_BYTES_PER_PX * px / (fused_ms * 1e-3) / 1e9
+    # launch duration of the dominant kernel: the per-step events above also
+    # hold each launch's dispatch latency (an event marker, then the kernel), so
+    # the part-2 kernel is also timed as a burst of back-to-back launches over the
+    # rotating sets, between two HIP events on the same stream
+    n_burst = 4 * len(sets)
+    b0 = torch.cuda.Event(enable_timing=True)
+    b1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    b0.record()
+    for i in range(n_burst):
+        s = sets[i % len(sets)]
+        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_POINTS,
+                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
+    b1.record()
+    torch.cuda.synchronize()
+    kern_ms = b0.elapsed_time(b1) / n_burst
+
+    achieved = FUSED_BYTES_PER_PX * px / (kern_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(f"k_stencil<0, {ng // 2}, {tiles[1]}>")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "kernel": f"k_stencil<0,{ng // 2},{tiles[1]}> (snx_pipeline part 2)",
-                "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(fused_ms, 5)}
+                "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(kern_ms, 5),
+                "launch_timing": f"HIP events around {n_burst} back-to-back launches",
+                "in_step_ms": round(fused_ms, 5)}
 
     batched = None if args.no_batched else bench_batched(args, snx, torch, np, dev, nf, ng)
     star = None if args.no_star else bench_star(snx, torch, np, dev, sc, cam, nf)
@@ -547,7 +575,8 @@ def main():
                    "filter_window": nf, "normal_window": ng, "k_rel": 0.1, "t_abs": 1.0,
                    "rotating_sets": len(sets), "working_set_MB": round(set_bytes * len(sets) / 1e6),
                    "tile_heights": {"fused": tiles[0], "gradient": tiles[1]}},
-        "stages_ms": {"part1_forest_filter": round(comp_ms, 5), "part2_points": round(fused_ms, 5)},
+        "stages_ms": {"part1_forest_filter": round(comp_ms, 5), "part2_points": round(fused_ms, 5),
+                      "timing": f"HIP event markers around each part, {n_split} further steps"},
         "mean_angular_error_deg": round(mean_err, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -150,10 +150,23 @@ def _check(status):
         raise SnxError(status, load().snx_last_error().decode())
 
 
+_current_raw_stream = None
+
+
 def _stream(stream):
-    import torch
+    """The raw HIP stream handle: the given stream, else torch's current stream
+    (read without building a Stream object: this runs on every call)."""
+    global _current_raw_stream
     if stream is None:
-        return torch.cuda.current_stream().cuda_stream
+        if _current_raw_stream is None:
+            import torch
+            raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+            if raw is not None:
+                dev = torch.cuda.current_device
+                _current_raw_stream = lambda: raw(dev())
+            else:
+                _current_raw_stream = lambda: torch.cuda.current_stream().cuda_stream
+        return _current_raw_stream()
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
