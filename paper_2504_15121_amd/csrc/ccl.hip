@@ -259,7 +259,17 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
         p = (y - 1) * W + x;
         q = p + W;
     }
-    g_union(par, p, q);
+    // Hook first: the entries of p and q are ancestors of them (their tile
+    // roots, or nearer the root after halving), so the larger is hooked under
+    // the smaller at once.  If it was still a root the union is done in two
+    // round trips; otherwise its old parent, like it an ancestor of one side,
+    // is united with the other side by the general path.
+    int a = gload(par + p), b = gload(par + q);
+    if (a == b) return;
+    if (a < b) { const int t = a; a = b; b = t; }
+    const int old = atomicMin(par + a, b);
+    if (old == a) return;
+    g_union(par, old, b);
 }
 
 __global__ void __launch_bounds__(256)
