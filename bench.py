@@ -50,6 +50,9 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per pixel of the part-2 kernel: filtered disparity in (4),
 # label forest in (4), final label out (4), one 32-byte point record out
 FUSED_BYTES_PER_PX = 4 + 4 + 4 + 32
+# the whole step's minimum: the raw disparity in, a 28-byte record of useful
+# fields out (x, y, z, normal, label)
+STEP_MIN_BYTES_PER_PX = 4 + 28
 
 
 def parse():
@@ -71,6 +74,12 @@ def parse():
                     help="distinct generated road frames (the rest are copies)")
     ap.add_argument("--uneven-frames", type=int, default=64)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the headline step and its roofline (no batch, sphere, small-frame, "
+                         "compaction, adaptive-support or CPU figures): the command of the "
+                         "committed kernel trace")
+    ap.add_argument("--tile-heights", default=None,
+                    help="FUSED,GRADIENT tile heights to pin instead of autotuning")
     ap.add_argument("--iso-sweep", action="store_true",
                     help="instead of the bench line: mean angular error and Mpixel/s of the plain "
                          "path over filter x gradient windows and of the learned path over "
@@ -83,8 +92,18 @@ def _pool_map(fn, items):
     n = max(1, min(16, os.cpu_count() or 1, len(items)))
     if n == 1:
         return [fn(x) for x in items]
-    with mp.get_context("spawn").Pool(n) as pool:
-        return pool.map(fn, items)
+    # close and join (not the context manager's terminate): the workers exit on
+    # their own instead of being signalled
+    pool = mp.get_context("spawn").Pool(n)
+    try:
+        res = pool.map(fn, items)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return res
 
 
 def _road(seed):
@@ -168,19 +187,46 @@ def bench_batched(args, snx, torch, np, dev, nf, ng):
     model = snx.cnn_model(P, packed, ws)
     road = {"workload": f"road_{n}x2048x1024", "frames": n, "distinct_frames": len(distinct),
             "megapixels": round(px / 1e6, 2), "normal_window": ng}
-    for tag, kw in (("learned_batched", dict(cnn=model)), ("plain_batched", dict(filter_window=nf))):
-        plan = snx.Plan(bufs, normal_window=ng, **kw)
-        ms = _time_replays(snx, torch, plan, stream, max(2, args.batch_steps // 2))
+    gts = [torch.from_numpy(f.normal.astype(np.float32)).to(dev) for f in distinct]
+
+    def run_plan(kw, window, steps):
+        plan = snx.Plan(bufs, normal_window=window, **kw)
+        ms = _time_replays(snx, torch, plan, stream, steps)
         es, ec = 0.0, 0
-        for i, f in enumerate(distinct):
-            e, c = angular_error_sum(bufs[i]["points"].cpu().numpy(), f.normal)
+        for i in range(len(distinct)):
+            e, c = _gpu_angles(torch, bufs[i]["points"], gts[i])
             es, ec = es + e, ec + c
-        road[tag] = {"ms_per_batch": round(ms, 3), "value": round(px / (ms * 1e-3) / 1e6, 1),
-                     "unit": "Mpixel/s", "mean_angular_error_deg": round(es / ec, 3),
-                     "filter": "cnn" if "cnn" in kw else f"lsq{nf}"}
         plan.close()
+        return ms, es / ec
+
+    for tag, kw in (("learned_batched", dict(cnn=model)), ("plain_batched", dict(filter_window=nf))):
+        ms, err = run_plan(kw, ng, max(2, args.batch_steps // 2))
+        road[tag] = {"ms_per_batch": round(ms, 3), "value": round(px / (ms * 1e-3) / 1e6, 1),
+                     "unit": "Mpixel/s", "mean_angular_error_deg": round(err, 3),
+                     "filter": "cnn" if "cnn" in kw else f"lsq{nf}"}
     road["learned_vs_plain_speed"] = round(road["learned_batched"]["value"] /
                                            road["plain_batched"]["value"], 3)
+    # iso-accuracy: both batched paths over gradient windows (plans take the 3x3
+    # LSQ filter or the network), compared at the 3 deg bound and pairwise at
+    # equal or lower error
+    points = []
+    for path, kw, windows in (("plain_batched", dict(filter_window=nf), (9, 21, 31, 45, 61)),
+                              ("learned_batched", dict(cnn=model), (9, 21, 31, 45))):
+        for w in windows:
+            if w == ng:
+                r = road[path]
+                ms, err = r["ms_per_batch"], r["mean_angular_error_deg"]
+            else:
+                ms, err = run_plan(kw, w, 2)
+            points.append({"path": path, "normal_window": w,
+                           "filter": "cnn" if "cnn" in kw else f"lsq{nf}",
+                           "mean_angular_error_deg": round(err, 3),
+                           "value": round(px / (ms * 1e-3) / 1e6, 1)})
+    iso = iso_accuracy(points, 3.0)
+    iso["points"] = points
+    iso["note"] = ("target: learned + batched faster than plain + batched at equal or lower "
+                   "mean angular error on held-out road frames")
+    road["iso_accuracy"] = iso
     out["road_batch"] = road
     del bufs
     torch.cuda.empty_cache()
@@ -418,6 +464,132 @@ def bench_star(snx, torch, np, dev, sc, cam, nf):
             "edge_band_px": int(band.sum()), "rows": rows}
 
 
+def _gpu_angles(torch, pts_or_n, gt_t, records=True):
+    """(sum of unsigned angles in degrees, count) between the normals of a
+    record tensor (H, W, 8) or a normal tensor (H, W, 3) and a ground-truth
+    tensor (H, W, 3) on the GPU, in float64."""
+    n = (pts_or_n[..., 3:6] if records else pts_or_n).double()
+    ok = torch.isfinite(n[..., 0]) & torch.isfinite(gt_t[..., 0])
+    a, b = n[ok], gt_t[ok].double()
+    cr = torch.linalg.norm(torch.cross(a, b, dim=-1), dim=-1)
+    ang = torch.rad2deg(torch.atan2(cr, (a * b).sum(-1).abs()))
+    return float(ang.sum().item()), int(ok.sum().item())
+
+
+def bench_small_frame(snx, torch, dev, nf, ng, replays=1000):
+    """The 640x480 three-plane frame, launch-bound: one captured batch plan of
+    the frame replayed `replays` times (and, for comparison, as many per-frame
+    snx_pipeline calls)."""
+    from synth import scenes
+    sc = scenes.workload("planes_640x480")
+    H, W = sc.disp.shape
+    f = dict(disp=torch.from_numpy(sc.disp).to(dev), cam=sc.cam,
+             labels=torch.empty((H, W), dtype=torch.int32, device=dev),
+             points=torch.empty((H, W, 8), device=dev),
+             num_components=torch.zeros(1, dtype=torch.int32, device=dev))
+    plan = snx.Plan([f], filter_window=nf, normal_window=ng)
+    stream = torch.cuda.Stream()
+    ms = _time_replays(snx, torch, plan, stream, replays, warmup=3)
+    plan.close()
+    ws = torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8, device=dev)
+    call = lambda: snx.snx_pipeline(f["disp"], sc.cam, f["labels"], f["points"], ws,
+                                    num_components=f["num_components"], filter_window=nf,
+                                    normal_window=ng)
+    for _ in range(3):
+        call()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(replays):
+        call()
+    b.record()
+    torch.cuda.synchronize()
+    ms_call = a.elapsed_time(b) / replays
+    return {"workload": "planes_640x480", "width": W, "height": H,
+            "graph_replays": replays, "us_per_frame_graph": round(ms * 1e3, 2),
+            "value_graph": round(W * H / (ms * 1e-3) / 1e6, 1),
+            "us_per_frame_calls": round(ms_call * 1e3, 2),
+            "value_calls": round(W * H / (ms_call * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
+            "filter": f"lsq{nf}", "normal_window": ng}
+
+
+def bench_sphere(snx, torch, np, dev, n=20):
+    """The paper's sphere workload (1024x1024, radius 1.4 at 3 units, baseline
+    0.3, f = 500 px assumed): no pre-filter, the square n_g window; time per
+    frame and mean angular error against the paper's table (Sec. 4, Affine
+    rows)."""
+    from synth import scenes
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "sphere_noise_table.json")))
+    rows = []
+    for key, sigma in (("sigma_0.2", 0.2), ("sigma_1.0", 1.0)):
+        sc = scenes.sphere_scene(sigma=sigma, seed=0)
+        H, W = sc.disp.shape
+        cam = sc.cam
+        d = torch.from_numpy(sc.disp).to(dev)
+        gt = torch.from_numpy(sc.normal).to(dev)
+        dn = torch.empty((H, W), device=dev)
+        nrm = torch.empty((3, H, W), device=dev)
+        for ng, paper in zip(tab["window"], tab[key]):
+            fn = lambda: (snx.snx_denoise(d, dn, window=1),
+                          snx.snx_affine_normals(dn, cam, normals=nrm, window=ng))
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(n):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / n
+            es, ec = _gpu_angles(torch, nrm.permute(1, 2, 0), gt, records=False)
+            rows.append({"sigma": sigma, "normal_window": ng, "ms_per_frame": round(ms, 4),
+                         "mpixel_per_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+                         "mean_err_deg": round(es / ec, 3), "paper_mean_err_deg": round(paper, 3)})
+    return {"workload": "sphere_1024x1024", "filter_window": 1, "noise_draw": "seed 0",
+            "rows": rows}
+
+
+def iso_accuracy(points, bound):
+    """From (tag, error, Mpixel/s) points of the two paths: per path the fastest
+    configuration within the error bound, else its lowest error; and for every
+    learned point the fastest plain point of equal or lower error."""
+    out = {"bound_deg": bound}
+    for path in ("plain_batched", "learned_batched"):
+        pts = [p for p in points if p["path"] == path]
+        ok = [p for p in pts if p["mean_angular_error_deg"] <= bound]
+        if ok:
+            best = max(ok, key=lambda p: p["value"])
+            out[path] = dict(best, within_bound=True)
+        else:
+            best = min(pts, key=lambda p: p["mean_angular_error_deg"])
+            out[path] = dict(best, within_bound=False)
+    pl, le = out["plain_batched"], out["learned_batched"]
+    if le["within_bound"]:
+        met = not pl["within_bound"] or le["value"] > pl["value"]
+    else:
+        met = False
+    out["learned_beats_plain_at_bound"] = met
+    pairs = []
+    for p in sorted((p for p in points if p["path"] == "learned_batched"),
+                    key=lambda p: p["mean_angular_error_deg"]):
+        rival = [q for q in points if q["path"] == "plain_batched"
+                 and q["mean_angular_error_deg"] <= p["mean_angular_error_deg"]]
+        q = max(rival, key=lambda q: q["value"]) if rival else None
+        pairs.append({"learned_normal_window": p["normal_window"],
+                      "learned_err_deg": p["mean_angular_error_deg"],
+                      "learned_value": p["value"],
+                      "fastest_plain_at_equal_or_lower_err":
+                          None if q is None else {"normal_window": q["normal_window"],
+                                                  "err_deg": q["mean_angular_error_deg"],
+                                                  "value": q["value"]},
+                      "learned_faster": q is None or p["value"] > q["value"]})
+    out["equal_error_pairs"] = pairs
+    return out
+
+
 def main():
     args = parse()
     if args.iso_sweep:
@@ -457,20 +629,29 @@ def main():
         ))
     set_bytes = sum(t.numel() * t.element_size() for t in sets[0].values())
 
+    def part(s, which):
+        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=which,
+                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
+
     def step(s, ev=None):
         if ev is not None:
             ev[0].record()
-        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_FOREST,
-                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
+        part(s, snx.PART_FOREST)
         if ev is not None:
             ev[1].record()
-        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_POINTS,
-                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
+        part(s, snx.PART_POINTS)
         if ev is not None:
             ev[2].record()
 
-    # pick tile heights for this frame size and these windows (set-up, untimed)
-    tiles = snx.snx_autotune(W, H, filter_window=nf, normal_window=ng)
+    # tile heights for this frame size and these windows (set-up, untimed)
+    if args.tile_heights:
+        th = [int(x) for x in args.tile_heights.split(",")]
+        snx.snx_tune_set(W, H, nf, ng, th[0])
+        if nf > 1:
+            snx.snx_tune_set(W, H, 1, ng, th[1])
+        tiles = (th[0], th[1] if nf > 1 else th[0])
+    else:
+        tiles = snx.snx_autotune(W, H, filter_window=nf, normal_window=ng)
 
     if args.copy_probe:
         a = torch.empty(128 << 20, dtype=torch.float32, device=dev)
@@ -517,53 +698,44 @@ def main():
     dt = np.abs((n[ok] * sc.normal[ok]).sum(-1))
     mean_err = float(np.degrees(np.arctan2(cr, dt)).mean())
 
-    # launch duration of the dominant kernel: the per-step events above also
-    # hold each launch's dispatch latency (an event marker, then the kernel), so
-    # the part-2 kernel is also timed as a burst of back-to-back launches over the
-    # rotating sets, between two HIP events on the same stream
-    n_burst = 4 * len(sets)
-    b0 = torch.cuda.Event(enable_timing=True)
-    b1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    b0.record()
-    for i in range(n_burst):
-        s = sets[i % len(sets)]
-        snx.snx_pipeline_part(s["d"], cam, s["lab"], s["pts"], s["ws"], parts=snx.PART_POINTS,
-                              num_components=s["cnt"], filter_window=nf, normal_window=ng)
-    b1.record()
-    torch.cuda.synchronize()
-    kern_ms = b0.elapsed_time(b1) / n_burst
+    # launch duration of the dominant kernel (part 2): bursts of back-to-back
+    # launches over the rotating sets between two HIP events on the stream the
+    # kernels run on, each launch on a set whose part 1 has just left an
+    # unresolved label forest (as in a step), so every launch does the step's
+    # full work
+    n_rep = 4
+    kern_total = 0.0
+    for _ in range(n_rep):
+        for s in sets:
+            part(s, snx.PART_FOREST)
+        torch.cuda.synchronize()
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record()
+        for s in sets:
+            part(s, snx.PART_POINTS)
+        b1.record()
+        torch.cuda.synchronize()
+        kern_total += b0.elapsed_time(b1)
+    n_burst = n_rep * len(sets)
+    kern_ms = kern_total / n_burst
 
     achieved = FUSED_BYTES_PER_PX * px / (kern_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(f"k_stencil<0, {ng // 2}, {tiles[1]}>")
+    step_gbs = STEP_MIN_BYTES_PER_PX * px / (ms_per_step * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "kernel": f"k_stencil<0,{ng // 2},{tiles[1]}> (snx_pipeline part 2)",
                 "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(kern_ms, 5),
-                "launch_timing": f"HIP events around {n_burst} back-to-back launches",
-                "in_step_ms": round(fused_ms, 5)}
-
-    batched = None if args.no_batched else bench_batched(args, snx, torch, np, dev, nf, ng)
-    star = None if args.no_star else bench_star(snx, torch, np, dev, sc, cam, nf)
-    compact = bench_compact(snx, torch, dev, sets[0], W, H)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        from oracle import oracle
-        oracle.load()
-        runs = []
-        oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)       # warm-up
-        t0 = time.perf_counter()
-        while len(runs) < 200 and (time.perf_counter() - t0 < 10.0 or len(runs) < 3):
-            t1 = time.perf_counter()
-            oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)
-            runs.append(time.perf_counter() - t1)
-        med = sorted(runs)[len(runs) // 2]
-        cpu = {"value": round(px / med / 1e6, 3), "unit": "Mpixel/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"full {W}x{H} frame, median of {len(runs)} runs "
-                         f"({sum(runs):.1f} s of CPU time)"}
+                "launch_timing": f"HIP events around {n_rep} bursts of {len(sets)} back-to-back "
+                                 "launches, each on a freshly built forest",
+                "in_step_ms": round(fused_ms, 5),
+                "whole_step": {"bytes_per_px": STEP_MIN_BYTES_PER_PX,
+                               "bytes_note": "the method's fused minimum: 4 B disparity in, "
+                                             "28 B of point record out",
+                               "achieved": round(step_gbs, 1),
+                               "frac": round(step_gbs / HBM_PEAK_GBS, 4)}}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
@@ -579,14 +751,70 @@ def main():
                       "timing": f"HIP event markers around each part, {n_split} further steps"},
         "mean_angular_error_deg": round(mean_err, 3),
         "roofline": roofline,
-        "cpu_baseline": cpu,
-        "compact_points": compact,
+        "cpu_baseline": None,
     }
-    if batched:
-        out.update(batched)
-    if star:
-        out["adaptive_support"] = star
+    if args.only_headline:
+        print(json.dumps(out), flush=True)
+        return
+
+    out["compact_points"] = bench_compact(snx, torch, dev, sets[0], W, H)
+    del sets
+    torch.cuda.empty_cache()
+    out["small_frame"] = bench_small_frame(snx, torch, dev, nf, ng)
+    out["sphere"] = bench_sphere(snx, torch, np, dev)
+    if not args.no_batched:
+        out.update(bench_batched(args, snx, torch, np, dev, nf, ng))
+    if not args.no_star:
+        out["adaptive_support"] = bench_star(snx, torch, np, dev, sc, cam, nf)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, cam, nf, ng, px)
     print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(sc, cam, nf, ng, px):
+    """The FP64 oracle pipeline on the full headline frame, on the host's OpenMP
+    threads and then on one thread (median of runs)."""
+    from oracle import oracle
+    oracle.load()
+
+    def timed(min_s, max_runs):
+        runs = []
+        oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)       # warm-up
+        t0 = time.perf_counter()
+        while len(runs) < max_runs and (time.perf_counter() - t0 < min_s or len(runs) < 3):
+            t1 = time.perf_counter()
+            oracle.pipeline(sc.disp, cam, nf=nf, ng=ng)
+            runs.append(time.perf_counter() - t1)
+        return sorted(runs)[len(runs) // 2], runs
+
+    threads = oracle.num_threads()
+    med, runs = timed(10.0, 200)
+    oracle.set_threads(1)
+    med1, runs1 = timed(4.0, 20)
+    oracle.set_threads(threads)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": round(px / med / 1e6, 3), "unit": "Mpixel/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full 1920x1080 frame, median of {len(runs)} runs "
+                      f"({sum(runs):.1f} s wall)",
+            "single_core": {"value": round(px / med1 / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+                            "sample": f"median of {len(runs1)} runs ({sum(runs1):.1f} s)"},
+            "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+                     "usable_cpus": affinity}}
 
 
 if __name__ == "__main__":

@@ -46,7 +46,9 @@ typedef enum snx_status {
     SNX_ERR_UNSUPPORTED = 2,  /* valid but unsupported (e.g. window too large)   */
     SNX_ERR_WORKSPACE = 3,    /* workspace missing or too small                   */
     SNX_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed       */
-    SNX_ERR_MODEL = 5         /* learned filter requested without a complete model */
+    SNX_ERR_MODEL = 5,        /* learned filter without a complete model, or a
+                                 corrupt / incompatible model file               */
+    SNX_ERR_IO = 6            /* a model file could not be opened, read or written */
 } snx_status;
 
 /* Rectified pin-hole pair (Sec. 2, projections Pi_1 and Pi_2): focal lengths in
@@ -160,8 +162,9 @@ snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride,
  * snx_affine_normals_star -- gradients, A and normals over the adaptive
  * star-fill support of Sec. 3.4 (Adaptive Region Estimation) instead of a
  * square window.  From a valid centre c, rays leave in `directions` = 4 (the
- * axes) or 8 (axes and diagonals) directions -- the angles 2 pi m / directions
- * with the step scaled to a unit larger component -- and take c + k e_m,
+ * axes), 8 (axes and diagonals) or 16 directions -- the angles
+ * 2 pi m / directions with the step scaled to a unit larger component -- and
+ * take c + round(k e_m) (each component rounded to the nearest pixel),
  * k = 1 .. steps (1..32), stopping before the first pixel that is invalid or
  * outside the image or meets the stopping rule:
  *   SNX_STOP_CD  covered depth: with a, b the smallest and largest disparity of
@@ -173,8 +176,9 @@ snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride,
  *                pixel is undefined (a 4-neighbour invalid or outside) or its
  *                magnitude exceeds `threshold` (baseline units).
  * Both rules are evaluated in binary64 on the float32 disparities.  The slope
- * is the anchored LSQ of snx_normal_params over the pixels the rays take (the
- * centre anchors it); it is defined iff they number at least min_support
+ * is the anchored LSQ of snx_normal_params over the pixels the rays take, each
+ * pixel once (with 16 directions neighbouring rays share their first pixel;
+ * the centre anchors the fit); it is defined iff they number at least min_support
  * (<= 0 selects `directions`) and alpha*gamma - beta^2 > 0.  A and the normal
  * follow as in snx_affine_normals, and the buffers are laid out the same way.
  * Other direction counts return SNX_ERR_UNSUPPORTED; steps outside 1..32, an
@@ -183,7 +187,7 @@ snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride,
 #define SNX_STOP_CD 0
 #define SNX_STOP_ST 1
 typedef struct snx_star_params {
-    int32_t directions;   /* 4 or 8 */
+    int32_t directions;   /* 4, 8 or 16 */
     int32_t steps;        /* 1 .. 32 pixels per ray */
     int32_t stop;         /* SNX_STOP_CD or SNX_STOP_ST */
     int32_t min_support;  /* <= 0: directions */
@@ -214,6 +218,23 @@ snx_status snx_components(const float *disp_raw, int64_t stride,
                           int32_t *num_components,
                           void *workspace, size_t workspace_bytes,
                           void *stream);
+
+/* snx_components_from_edges -- the labelling of snx_components on a 4-neighbour
+ * graph given explicitly instead of by the covered-depth predicate, so that
+ * every edge pattern can be posed independently of pixel validity (a test hook
+ * for exhaustive checks of the union-find; Sec. 3.4 defines the regions the
+ * predicate builds).  edges [height x stride] uint8, one byte per pixel:
+ * bit 0 = the pixel is present, bit 1 = edge to its left neighbour (u - 1),
+ * bit 2 = edge to its upper neighbour (v - 1); other bits are ignored, and an
+ * edge counts only between two present pixels (bits on the image border are
+ * ignored).  Labels, count, workspace and errors as in snx_components (absent
+ * pixels get -1). */
+snx_status snx_components_from_edges(const uint8_t *edges, int64_t stride,
+                                     int32_t width, int32_t height,
+                                     int32_t *labels, int64_t label_stride,
+                                     int32_t *num_components,
+                                     void *workspace, size_t workspace_bytes,
+                                     void *stream);
 
 /* ---------------------------------------------------------------------------
  * snx_components_creases -- snx_components where every 4-neighbour edge must
@@ -415,6 +436,60 @@ snx_status snx_cnn_train_step(const float *disp, const float *normals, const flo
                               float *adam_m, float *adam_v, int32_t step, float lr,
                               float beta1, float beta2, float eps, double *loss_out,
                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* ===========================================================================
+ * Model files of the learned denoiser.  A model holds the FP32 parameters (the
+ * layout of snx_cnn_param_count), optionally the two Adam moments, the
+ * optimiser step and a few training facts, on the host; snx_model_bind makes
+ * device copies for snx_denoise / snx_pipeline / snx_plan_create.
+ *
+ * File layout, little-endian, version 1:
+ *    0  char[4]   magic "SNXM"
+ *    4  uint32    version (1)
+ *    8  uint32    parameter count n (must equal snx_cnn_param_count())
+ *   12  uint32    flags: bit 0 = the Adam moments follow the parameters
+ *   16  int64     optimiser step
+ *   24  int32     gradient window the model was trained with (0 = unknown)
+ *   28  int32     training seed
+ *   32  float32   weight of the fidelity term
+ *   36  uint32    reserved (0)
+ *   40  float32[n] parameters, then with bit 0 float32[n] first and float32[n]
+ *                  second Adam moments
+ *  end  uint32    CRC-32 (reflected polynomial 0xEDB88320, as zlib's crc32) of
+ *                  every byte before it
+ * A file of any other length, magic, version, count, flags or checksum is
+ * refused with SNX_ERR_MODEL; open/read/write failures give SNX_ERR_IO.
+ * These calls (except snx_model_bind) are host-only: they need no GPU.
+ * ========================================================================= */
+typedef struct snx_model snx_model;
+typedef struct snx_model_info {
+    int64_t step;
+    int32_t normal_window;
+    int32_t seed;
+    float fidelity;
+    int32_t has_moments;      /* output only: 1 if the model holds Adam moments */
+} snx_model_info;
+
+/* New model from host arrays of snx_cnn_param_count() floats (copied); adam_m
+ * and adam_v both NULL (no Adam state) or both set; info may be NULL. */
+snx_status snx_model_create(const float *params, const float *adam_m, const float *adam_v,
+                            const snx_model_info *info, snx_model **model);
+/* Reads and checks a model file; *model is NULL on failure. */
+snx_status snx_model_load(const char *path, snx_model **model);
+/* Writes the model to `path` atomically: to "<path>.tmp", then renamed. */
+snx_status snx_model_save(const snx_model *model, const char *path);
+/* Copies out the parameters, the moments (SNX_ERR_MODEL if asked for and
+ * absent) and the info; each output may be NULL. */
+snx_status snx_model_read(const snx_model *model, float *params, float *adam_m, float *adam_v,
+                          snx_model_info *info);
+/* Device copies of the parameters, packed weights and a workspace for frames up
+ * to width x height, owned by the model (kept until snx_model_destroy, grown by
+ * later binds); fills *view for the learned filter.  A set-up call: allocates
+ * and synchronizes `stream`. */
+snx_status snx_model_bind(snx_model *model, int32_t width, int32_t height, void *stream,
+                          snx_cnn_model *view);
+/* Frees the model and its device copies (NULL is a no-op). */
+snx_status snx_model_destroy(snx_model *model);
 
 /* ===========================================================================
  * Batch plans: many frames of uneven size through the whole path (filter or

@@ -11,6 +11,7 @@ Stage functions (the C file cites the paper's passage for each):
   normals(Dt, a1, a2, ...)  normal from the constraint-vector cross product
   components(D, k, t)       min-index labels of covered-depth components
   components_crease(D, n, ...) the same with a normal-crease test on every edge
+  components_edges(flags)   the same on an explicitly given 4-neighbour graph
   point_cloud(Dt, n, cam)   back-projected points with normals
   affine_labels(Dt, lab, ng) a1, a2 over the window restricted to the centre's component
   compact_points(rec)       the defined records of a dense cloud in raster order
@@ -49,8 +50,10 @@ def load():
     lib.snxo_normals.argtypes = [_dp, _dp, _dp, _u8, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
     lib.snxo_components.argtypes = [_fp, C.c_int, C.c_int, C.c_float, C.c_float, _i32,
                                     C.POINTER(C.c_int64)]
+    lib.snxo_components_edges.argtypes = [_u8, C.c_int, C.c_int, _i32, C.POINTER(C.c_int64)]
     lib.snxo_point_cloud.argtypes = [_dp, _dp, C.c_int, C.c_int] + [C.c_double] * 5 + [_dp]
     lib.snxo_num_threads.argtypes = []
+    lib.snxo_set_threads.argtypes = [C.c_int]
     lib.snxo_components_crease.argtypes = [_fp, _fp, C.c_int, C.c_int, C.c_float, C.c_float,
                                            C.c_double, _i32, C.POINTER(C.c_int64)]
     lib.snxo_affine_labels.argtypes = [_dp, _i32, C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp,
@@ -61,7 +64,8 @@ def load():
                                      C.c_double, C.c_double, C.c_int, _dp, _dp, _u8]
     for f in ("snxo_denoise", "snxo_affine", "snxo_normals", "snxo_components",
               "snxo_point_cloud", "snxo_num_threads", "snxo_star_mask", "snxo_star_affine",
-              "snxo_affine_labels", "snxo_components_crease"):
+              "snxo_affine_labels", "snxo_components_crease", "snxo_components_edges",
+              "snxo_set_threads"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -69,6 +73,11 @@ def load():
 
 def num_threads() -> int:
     return int(load().snxo_num_threads())
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of later calls; returns the count now in effect."""
+    return int(load().snxo_set_threads(int(n)))
 
 
 def default_min_support(ng: int) -> int:
@@ -121,6 +130,19 @@ def components(D, k_rel: float = 0.1, t_abs: float = 1.0):
         raise MemoryError("oracle components")
     return lab, int(n.value)
 
+
+
+def components_edges(flags):
+    """Labels and count of the 4-neighbour graph given by per-pixel bits:
+    bit 0 present, bit 1 edge to the left neighbour, bit 2 edge to the upper
+    neighbour (an edge counts between two present pixels)."""
+    flags = np.ascontiguousarray(flags, dtype=np.uint8)
+    H, W = flags.shape
+    lab = np.empty((H, W), np.int32)
+    n = C.c_int64(0)
+    if load().snxo_components_edges(flags, W, H, lab, C.byref(n)) != 0:
+        raise MemoryError("oracle components_edges")
+    return lab, int(n.value)
 
 def point_cloud(Dt, nrm, cam) -> np.ndarray:
     Dt = _as_f64(Dt)

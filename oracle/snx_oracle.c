@@ -41,6 +41,9 @@
  *                       anchored LSQ
  */
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -329,6 +332,58 @@ int snxo_components(const float *D, int W, int H, float k_rel, float t_abs,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Components of an explicitly given 4-neighbour graph (the test hook of the  */
+/* labelling: every edge pattern can be posed, independently of validity).   */
+/* flags[v * W + u]: bit 0 = pixel present, bit 1 = edge to (u - 1, v),      */
+/* bit 2 = edge to (u, v - 1); an edge counts only between two present       */
+/* pixels.  Labels and count as snxo_components (BFS in raster order).       */
+/* ------------------------------------------------------------------------ */
+/* Edge between p and its neighbour q in direction k (0 left, 1 right, 2 up,
+ * 3 down): the bit sits on the right or lower pixel of the pair. */
+static int edge_bits(const uint8_t *f, int64_t p, int64_t q, int k)
+{
+    if (!(f[p] & 1) || !(f[q] & 1)) return 0;
+    switch (k) {
+    case 0: return (f[p] >> 1) & 1;
+    case 1: return (f[q] >> 1) & 1;
+    case 2: return (f[p] >> 2) & 1;
+    default: return (f[q] >> 2) & 1;
+    }
+}
+
+int snxo_components_edges(const uint8_t *flags, int W, int H, int32_t *labels,
+                          int64_t *num_components)
+{
+    const int64_t N = (int64_t)W * H;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(N > 0 ? N : 1));
+    if (!queue) return 2;
+    for (int64_t i = 0; i < N; ++i) labels[i] = -1;
+    int64_t count = 0;
+    for (int64_t s = 0; s < N; ++s) {
+        if (labels[s] != -1 || !(flags[s] & 1)) continue;
+        ++count;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        labels[s] = (int32_t)s;
+        while (head < tail) {
+            const int64_t p = queue[head++];
+            const int u = (int)(p % W), v = (int)(p / W);
+            const int64_t nb[4] = {u > 0 ? p - 1 : -1, u + 1 < W ? p + 1 : -1,
+                                   v > 0 ? p - W : -1, v + 1 < H ? p + W : -1};
+            for (int k = 0; k < 4; ++k) {
+                const int64_t q = nb[k];
+                if (q < 0 || labels[q] != -1 || !edge_bits(flags, p, q, k)) continue;
+                labels[q] = (int32_t)s;
+                queue[tail++] = q;
+            }
+        }
+    }
+    free(queue);
+    *num_components = count;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Crease-aware components: as snxo_components, and an edge also needs the   */
 /* two pixels' unit normals (float32 planes nrm[0..2][v * W + u]) to agree:   */
 /*   n_p . n_q = ((nx_p nx_q + ny_p ny_q) + nz_p nz_q) >= cos_min             */
@@ -411,12 +466,12 @@ int snxo_point_cloud(const double *Dt, const double *nrm, int W, int H,
 
 /* ------------------------------------------------------------------------ */
 /* Adaptive star-fill support (Sec. 3.4, Adaptive Region Estimation).        */
-/* From a valid centre c, rays leave in M = 4 or 8 directions e_m: the       */
+/* From a valid centre c, rays leave in M = 4, 8 or 16 directions e_m: the  */
 /* directions at angles 2 pi m / M scaled so that their larger component is  */
-/* 1, i.e. the compass directions (for M = 8 the axes and the diagonals, for */
-/* M = 4 the axes).  Ray m takes the pixels c + k e_m, k = 1 .. steps, in    */
-/* order, and stops before the first one that is invalid or outside the      */
-/* image or meets the stopping rule:                                         */
+/* 1 (for M = 8 the axes and the diagonals, for M = 4 the axes).  Ray m      */
+/* takes the pixels c + round(k e_m), k = 1 .. steps, in order, and stops    */
+/* before the first one that is invalid or outside the image or meets the    */
+/* stopping rule:                                                            */
 /*   CD  covered depth: with a, b the smallest and the largest disparity of  */
 /*       c and of the ray's pixels up to and including the new one, stop     */
 /*       when D_c (b - a) > k (a b): the depth range f_x B (1/a - 1/b)        */
@@ -426,13 +481,24 @@ int snxo_point_cloud(const double *Dt, const double *nrm, int W, int H,
 /*       L = ((z_r + z_l) + (z_d + z_u)) - 4 z  at the new pixel, with        */
 /*       z = fxb / D (binary64), is undefined (a 4-neighbour invalid or       */
 /*       outside the image) or |L| > t.                                       */
-/* The support is the set of pixels taken by the rays; c anchors the fit.    */
+/* The support is the set of pixels taken by the rays (their union: for     */
+/* M = 16 neighbouring rays share their first pixel); c anchors the fit.     */
 /* ------------------------------------------------------------------------ */
 #define SNXO_STOP_CD 0
 #define SNXO_STOP_ST 1
 
-static const int kStarDir8[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1},
-                                    {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+/* Offset of step k along ray m of M (Sec. 3.4 star fill; the rasterisation is a
+ * reading): the direction at angle 2 pi m / M, scaled so that its larger
+ * component is 1, times k, each component rounded to the nearest pixel.  For
+ * M = 4 and 8 this gives the axes and the diagonals exactly. */
+static void star_offset(int m, int M, int k, int *dx, int *dy)
+{
+    const double th = 2.0 * M_PI * (double)m / (double)M;
+    const double c = cos(th), s = sin(th);
+    const double big = fabs(c) > fabs(s) ? fabs(c) : fabs(s);
+    *dx = (int)lround((double)k * c / big);
+    *dy = (int)lround((double)k * s / big);
+}
 
 static int star_valid_at(const double *Dt, int W, int H, int u, int v)
 {
@@ -460,7 +526,8 @@ static int star_st_edge(const double *Dt, int W, int H, int u, int v, double fxb
 int snxo_star_mask(const double *Dt, int W, int H, int u, int v, int dirs, int steps,
                    int stop, double thr, double fxb, uint8_t *mask)
 {
-    if ((dirs != 4 && dirs != 8) || steps < 1 || (stop != SNXO_STOP_CD && stop != SNXO_STOP_ST))
+    if ((dirs != 4 && dirs != 8 && dirs != 16) || steps < 1 ||
+        (stop != SNXO_STOP_CD && stop != SNXO_STOP_ST))
         return -1;
     const int side = 2 * steps + 1;
     memset(mask, 0, (size_t)side * side);
@@ -468,10 +535,11 @@ int snxo_star_mask(const double *Dt, int W, int H, int u, int v, int dirs, int s
     const double Dc = Dt[(int64_t)v * W + u];
     int count = 0;
     for (int m = 0; m < dirs; ++m) {
-        const int *e = kStarDir8[m * (8 / dirs)];
         double a = Dc, b = Dc;
         for (int k = 1; k <= steps; ++k) {
-            const int uu = u + k * e[0], vv = v + k * e[1];
+            int ox, oy;
+            star_offset(m, dirs, k, &ox, &oy);
+            const int uu = u + ox, vv = v + oy;
             if (!star_valid_at(Dt, W, H, uu, vv)) break;
             const double Di = Dt[(int64_t)vv * W + uu];
             if (stop == SNXO_STOP_CD) {
@@ -482,7 +550,8 @@ int snxo_star_mask(const double *Dt, int W, int H, int u, int v, int dirs, int s
             } else if (star_st_edge(Dt, W, H, uu, vv, fxb, thr)) {
                 break;
             }
-            uint8_t *mk = &mask[(k * e[1] + steps) * side + k * e[0] + steps];
+            /* the support is the union of the pixels the rays visit */
+            uint8_t *mk = &mask[(oy + steps) * side + ox + steps];
             if (!*mk) { *mk = 1; ++count; }
         }
     }
@@ -497,7 +566,7 @@ int snxo_star_affine(const double *Dt, int W, int H, int dirs, int steps, int st
                      double thr, double fxb, int min_support, double *a1, double *a2,
                      uint8_t *defined)
 {
-    if ((dirs != 4 && dirs != 8) || steps < 1 || steps > 64 || W < 1 || H < 1 ||
+    if ((dirs != 4 && dirs != 8 && dirs != 16) || steps < 1 || steps > 64 || W < 1 || H < 1 ||
         (stop != SNXO_STOP_CD && stop != SNXO_STOP_ST))
         return 1;
     const int side = 2 * steps + 1;
@@ -553,6 +622,18 @@ int snxo_num_threads(void)
 #ifdef _OPENMP
     return omp_get_max_threads();
 #else
+    return 1;
+#endif
+}
+
+/* Threads of later calls (the CPU baseline is timed on all cores and on one). */
+int snxo_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
     return 1;
 #endif
 }

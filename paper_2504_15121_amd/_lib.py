@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libsnx.so")
 
 SNX_OK = 0
 STATUS = {0: "SNX_OK", 1: "SNX_ERR_ARG", 2: "SNX_ERR_UNSUPPORTED", 3: "SNX_ERR_WORKSPACE",
-          4: "SNX_ERR_HIP", 5: "SNX_ERR_MODEL"}
+          4: "SNX_ERR_HIP", 5: "SNX_ERR_MODEL", 6: "SNX_ERR_IO"}
 
 POINT_DEFINED = 1
 POINT_LABELLED = 2
@@ -40,6 +40,11 @@ class snx_denoise_params(C.Structure):
 class snx_cnn_model(C.Structure):
     _fields_ = [("params", C.c_void_p), ("packed", C.c_void_p), ("workspace", C.c_void_p),
                 ("workspace_bytes", C.c_size_t)]
+
+
+class snx_model_info(C.Structure):
+    _fields_ = [("step", C.c_int64), ("normal_window", C.c_int32), ("seed", C.c_int32),
+                ("fidelity", C.c_float), ("has_moments", C.c_int32)]
 
 
 class snx_frame(C.Structure):
@@ -112,6 +117,13 @@ SIGNATURES = {
     "snx_cnn_train_step": (_I32, [_P, _P, _P, C.c_float, _P, _I32, _I32, _I32, _I32, _P, _P,
                                   _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float,
                                   _P, _P, _SZ, _P]),
+    "snx_components_from_edges": (_I32, [_P, _I64, _I32, _I32, _P, _I64, _P, _P, _SZ, _P]),
+    "snx_model_create": (_I32, [_P, _P, _P, C.POINTER(snx_model_info), C.POINTER(C.c_void_p)]),
+    "snx_model_load": (_I32, [C.c_char_p, C.POINTER(C.c_void_p)]),
+    "snx_model_save": (_I32, [_P, C.c_char_p]),
+    "snx_model_read": (_I32, [_P, _P, _P, _P, C.POINTER(snx_model_info)]),
+    "snx_model_bind": (_I32, [_P, _I32, _I32, _P, C.POINTER(snx_cnn_model)]),
+    "snx_model_destroy": (_I32, [_P]),
     "snx_plan_create": (_I32, [_P, _I32, C.POINTER(snx_denoise_params),
                                C.POINTER(snx_normal_params), C.POINTER(snx_component_params),
                                C.POINTER(C.c_void_p)]),
@@ -327,6 +339,17 @@ def snx_components(disp, labels, workspace, num_components=None, k_rel=0.1, t_ab
                                  workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
+def snx_components_from_edges(edges, labels, workspace, num_components=None, stream=None):
+    """Components of the 4-neighbour graph given by per-pixel bits (uint8 (H, W):
+    bit 0 present, bit 1 edge left, bit 2 edge up); the labelling's test hook."""
+    import torch
+    H, W = edges.shape
+    _check(load().snx_components_from_edges(
+        _ptr(edges), _img(edges, torch.uint8, "edges"), W, H, _ptr(labels),
+        _img(labels, torch.int32, "labels"), _ptr(num_components), _ptr(workspace),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
 def _points(t, H, W):
     if t.numel() * t.element_size() < H * W * 32 or not t.is_contiguous() or not t.is_cuda:
         raise ValueError("points: need a contiguous CUDA buffer of width*height*32 bytes")
@@ -500,6 +523,54 @@ def snx_cnn_train_step(disp, normals, cams, params, packed, grad, adam_m, adam_v
         float(lr), float(beta1), float(beta2), float(eps),
         _dense(loss_out, torch.float64, (4,), "loss_out"), workspace.data_ptr(),
         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def model_save(path, params, adam_m=None, adam_v=None, step=0, normal_window=0, seed=0,
+               fidelity=0.0):
+    """Writes a model file (snx_model_create + snx_model_save) from host float32
+    arrays of snx_cnn_param_count() values; the moments both or neither."""
+    import numpy as np
+    n = snx_cnn_param_count()
+    arrs = []
+    for a in (params, adam_m, adam_v):
+        if a is None:
+            arrs.append(None)
+            continue
+        a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+        if a.size != n:
+            raise ValueError(f"need {n} values, got {a.size}")
+        arrs.append(a)
+    info = snx_model_info(int(step), int(normal_window), int(seed), float(fidelity), 0)
+    h = C.c_void_p()
+    lib = load()
+    _check(lib.snx_model_create(*[None if a is None else a.ctypes.data for a in arrs],
+                                C.byref(info), C.byref(h)))
+    try:
+        _check(lib.snx_model_save(h, os.fsencode(path)))
+    finally:
+        lib.snx_model_destroy(h)
+
+
+def model_load(path):
+    """Reads a model file (snx_model_load + snx_model_read): dict with params, m,
+    v (None without Adam state), step, normal_window, seed, fidelity."""
+    import numpy as np
+    lib = load()
+    h = C.c_void_p()
+    _check(lib.snx_model_load(os.fsencode(path), C.byref(h)))
+    try:
+        n = snx_cnn_param_count()
+        info = snx_model_info()
+        _check(lib.snx_model_read(h, None, None, None, C.byref(info)))
+        p = np.empty(n, np.float32)
+        m = np.empty(n, np.float32) if info.has_moments else None
+        v = np.empty(n, np.float32) if info.has_moments else None
+        _check(lib.snx_model_read(h, p.ctypes.data, None if m is None else m.ctypes.data,
+                                  None if v is None else v.ctypes.data, None))
+    finally:
+        lib.snx_model_destroy(h)
+    return dict(params=p, m=m, v=v, step=int(info.step), normal_window=int(info.normal_window),
+                seed=int(info.seed), fidelity=float(info.fidelity))
 
 
 class Plan:

@@ -124,6 +124,15 @@ snx_status api_fail(snx_status st, const char *msg)
     return fail(st, "%s", msg);
 }
 snx_status api_hip_fail(hipError_t e, const char *where) { return hip_fail(e, where); }
+void api_clear() { g_err[0] = 0; }
+snx_status api_failf(snx_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
 }  // namespace snx
 
 extern "C" {
@@ -137,6 +146,7 @@ const char *snx_status_string(snx_status s)
     case SNX_ERR_WORKSPACE: return "SNX_ERR_WORKSPACE";
     case SNX_ERR_HIP: return "SNX_ERR_HIP";
     case SNX_ERR_MODEL: return "SNX_ERR_MODEL";
+    case SNX_ERR_IO: return "SNX_ERR_IO";
     }
     return "SNX_ERR_UNKNOWN";
 }
@@ -277,8 +287,9 @@ snx_status snx_affine_normals_star(const float *disp_dn, int64_t stride, int32_t
     if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
     if (!params) return fail(SNX_ERR_ARG, "params is NULL");
     if (params->directions <= 0) return fail(SNX_ERR_ARG, "directions %d", params->directions);
-    if (params->directions != 4 && params->directions != 8)
-        return fail(SNX_ERR_UNSUPPORTED, "directions %d (4 or 8 supported)", params->directions);
+    if (params->directions != 4 && params->directions != 8 && params->directions != 16)
+        return fail(SNX_ERR_UNSUPPORTED, "directions %d (4, 8 or 16 supported)",
+                    params->directions);
     if (params->steps < 1 || params->steps > 32)
         return fail(SNX_ERR_ARG, "steps %d outside 1..32", params->steps);
     if (params->stop != SNX_STOP_CD && params->stop != SNX_STOP_ST)
@@ -365,6 +376,38 @@ snx_status snx_components(const float *disp_raw, int64_t stride, int32_t width, 
     return components_impl(disp_raw, stride, width, height, params, labels, label_stride,
                            num_components, workspace, workspace_bytes, (hipStream_t)stream,
                            "snx_components");
+}
+
+snx_status snx_components_from_edges(const uint8_t *edges, int64_t stride, int32_t width,
+                                     int32_t height, int32_t *labels, int64_t label_stride,
+                                     int32_t *num_components, void *workspace,
+                                     size_t workspace_bytes, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    hipStream_t s = (hipStream_t)stream;
+    if (width == 0 || height == 0) {
+        if (!num_components) return SNX_OK;
+        hipError_t e = snx::launch_fill_i32(num_components, 0, 1, s);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_components_from_edges");
+    }
+    snx_status st;
+    if ((st = check_image(edges, stride, width, "edges"))) return st;
+    if ((st = check_image(labels, label_stride, width, "labels"))) return st;
+    if (!workspace || workspace_bytes < ws_components(width, height))
+        return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_components(width, height));
+    snx::CclArgs c = {};
+    c.ld = stride;
+    c.W = width;
+    c.H = height;
+    c.labels = labels;
+    c.ld_lab = label_stride;
+    c.parent = label_stride == width ? labels : reinterpret_cast<int32_t *>(
+                                                    static_cast<char *>(workspace) + 256);
+    c.count = num_components;
+    c.edges = edges;
+    hipError_t e = snx::launch_components(c, s);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_components_from_edges");
 }
 
 snx_status snx_components_creases(const float *disp_raw, int64_t stride, const float *normals,

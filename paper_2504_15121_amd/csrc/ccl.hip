@@ -21,7 +21,9 @@
 namespace snx {
 namespace {
 
-constexpr int kFrontWaves = 4;
+constexpr int kFrontWaves = 8;   // 512 threads per 64 x 32 tile: four rows per wave
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Loads that bypass the per-CU L1 (the merge runs concurrently with hooks done
 // by other CUs).
@@ -70,6 +72,25 @@ __device__ __forceinline__ void g_union(int32_t *par, int a, int b)
     }
 }
 
+// The tile's local forest as global indices of each pixel's local root (-1 for
+// an invalid pixel).
+__device__ __forceinline__ void write_forest(const FrontArgs &a, const int *par, int x0, int y0,
+                                             int lane, int wave)
+{
+    const int gx = x0 + lane;
+    for (int ly = wave; ly < kCH; ly += kFrontWaves) {
+        const int gy = y0 + ly;
+        if (gx >= a.W || gy >= a.H) continue;
+        const int l = ly * kCW + lane;
+        int g = -1;
+        if (par[l] >= 0) {
+            const int r = lds_find(par, l);
+            g = (y0 + (r >> 6)) * a.W + x0 + (r & 63);
+        }
+        a.forest[(int64_t)gy * a.W + gx] = g;
+    }
+}
+
 template <int RF, bool CREASE = false>
 struct FrontSmem {
     static constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
@@ -91,22 +112,62 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x0 = bx * kCW, y0 = by * kCH;
 
-    // issue every load of the tile before the first wait
-    constexpr int NT = inH * inW, NL = (NT + kFrontWaves * 64 - 1) / (kFrontWaves * 64);
-    float v[NL];
+    // issue every load of the tile before the first wait.  A tile inside the
+    // frame horizontally with 16-byte aligned rows reads the 64 columns of each
+    // row as 16 aligned 16-byte loads and the two halo columns as single floats
+    // (no sector is fetched for a one-float overhang); other tiles read element
+    // by element.
+    constexpr int NTH = kFrontWaves * 64;
+    const int tid = threadIdx.x;
+    if (x0 + kCW <= a.W && (a.ld & 3) == 0 && ((uintptr_t)a.D & 15) == 0) {
+        constexpr int NB4 = inH * (kCW / 4), NL4 = (NB4 + NTH - 1) / NTH;
+        f32x4 b4[NL4];
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int e = threadIdx.x + k * kFrontWaves * 64;
-        const int ly = e / inW, lx = e - ly * inW;
-        const int gy = y0 - RF + ly, gx = x0 - RF + lx;
-        v[k] = 0.0f;
-        if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-            v[k] = __builtin_nontemporal_load(a.D + (int64_t)gy * a.ld + gx);
-    }
+        for (int k = 0; k < NL4; ++k) {
+            const int e = tid + k * NTH;
+            const int ly = e / (kCW / 4), c = e - ly * (kCW / 4);
+            const int gy = y0 - RF + ly;
+            b4[k] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+            if (e < NB4 && gy >= 0 && gy < a.H)
+                b4[k] = __builtin_nontemporal_load(
+                    reinterpret_cast<const f32x4 *>(a.D + (int64_t)gy * a.ld + x0) + c);
+        }
+        float hv = 0.0f;
+        const int hly = tid >> 1, hside = tid & 1;
+        if (RF > 0 && tid < 2 * inH) {
+            const int gy = y0 - RF + hly, gx = hside ? x0 + kCW : x0 - 1;
+            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                hv = __builtin_nontemporal_load(a.D + (int64_t)gy * a.ld + gx);
+        }
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        const int e = threadIdx.x + k * kFrontWaves * 64;
-        if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
+        for (int k = 0; k < NL4; ++k) {
+            const int e = tid + k * NTH;
+            if (e < NB4) {
+                const int ly = e / (kCW / 4), c = e - ly * (kCW / 4);
+                float *d = sIn + ly * inW + RF + 4 * c;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) d[i] = valid_disp(b4[k][i]) ? b4[k][i] : 0.0f;
+            }
+        }
+        if (RF > 0 && tid < 2 * inH)
+            sIn[hly * inW + (hside ? inW - 1 : 0)] = valid_disp(hv) ? hv : 0.0f;
+    } else {
+        constexpr int NT = inH * inW, NL = (NT + NTH - 1) / NTH;
+        float v[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = tid + k * NTH;
+            const int ly = e / inW, lx = e - ly * inW;
+            const int gy = y0 - RF + ly, gx = x0 - RF + lx;
+            v[k] = 0.0f;
+            if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                v[k] = __builtin_nontemporal_load(a.D + (int64_t)gy * a.ld + gx);
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = tid + k * NTH;
+            if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
+        }
     }
     if (CREASE) {
         for (int e = threadIdx.x; e < 3 * kCH * kCW; e += kFrontWaves * 64) {
@@ -135,28 +196,40 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
     if (CREASE) {
         const float *n = sm.nrm;
         constexpr int P = kCH * kCW;
-        local_forest(val, par, sm.hmask, lane, wave, kFrontWaves, a.k_rel, a.t_abs,
-                     [&](int la, int xa, int lb, int xb) {
-                         const int i = la * kCW + xa, j = lb * kCW + xb;
-                         return crease_ok(n[i], n[P + i], n[2 * P + i], n[j], n[P + j], n[2 * P + j],
-                                          a.crease_cos);
-                     });
+        local_forest(disp_edges(val,
+                                [&](int la, int xa, int lb, int xb) {
+                                    const int i = la * kCW + xa, j = lb * kCW + xb;
+                                    return crease_ok(n[i], n[P + i], n[2 * P + i], n[j], n[P + j],
+                                                     n[2 * P + j], a.crease_cos);
+                                },
+                                a.k_rel, a.t_abs),
+                     par, sm.hmask, lane, wave, kFrontWaves);
     } else {
-        local_forest(val, par, sm.hmask, lane, wave, kFrontWaves, a.k_rel, a.t_abs,
-                     [](int, int, int, int) { return true; });
+        local_forest(disp_edges(val, [](int, int, int, int) { return true; }, a.k_rel, a.t_abs),
+                     par, sm.hmask, lane, wave, kFrontWaves);
     }
+    write_forest(a, par, x0, y0, lane, wave);
+}
 
-    for (int ly = wave; ly < kCH; ly += kFrontWaves) {
-        const int gy = y0 + ly;
-        if (gx >= a.W || gy >= a.H) continue;
-        const int l = ly * kCW + lane;
-        int g = -1;
-        if (par[l] >= 0) {
-            const int r = lds_find(par, l);
-            g = (y0 + (r >> 6)) * a.W + x0 + (r & 63);
-        }
-        a.forest[(int64_t)gy * a.W + gx] = g;
+
+// Local forests of an explicitly given edge graph (the labelling's test hook):
+// per-pixel bits as in BitTileEdges, row stride a.ld_edges.
+__global__ void __launch_bounds__(kFrontWaves * 64)
+k_front_edges(FrontArgs a)
+{
+    __shared__ uint8_t f[kCH * kCW];
+    __shared__ int par[kCH * kCW];
+    __shared__ unsigned long long hmask[kCH];
+    if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x0 = blockIdx.x * kCW, y0 = blockIdx.y * kCH;
+    for (int e = threadIdx.x; e < kCH * kCW; e += kFrontWaves * 64) {
+        const int gy = y0 + (e >> 6), gx = x0 + (e & 63);
+        f[e] = gy < a.H && gx < a.W ? a.edges[(int64_t)gy * a.ld_edges + gx] : (uint8_t)0;
     }
+    __syncthreads();
+    local_forest(BitTileEdges{f}, par, hmask, lane, wave, kFrontWaves);
+    write_forest(a, par, x0, y0, lane, wave);
 }
 
 template <int RF, bool CREASE>
@@ -164,8 +237,10 @@ __global__ void __launch_bounds__(kFrontWaves * 64)
 k_front(FrontArgs a)
 {
     __shared__ FrontSmem<RF, CREASE> sm;
-    if (a.count && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.count = 0;
-    front_tile<RF, CREASE>(a, blockIdx.x, blockIdx.y, sm);
+    if (a.count && blockIdx.x == 0 && threadIdx.x == 0) *a.count = 0;
+    const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
+    const int t = xcd_tile(blockIdx.x, tx * ty);
+    front_tile<RF, CREASE>(a, t % tx, t / tx, sm);
 }
 
 // Persistent front over the (frame, tile) work list of a batch: workgroups
@@ -214,62 +289,103 @@ __device__ __forceinline__ bool seam_crease(const float *nrm, int64_t ld_nrm, in
                      nrm[2 * plane + j], ccos);
 }
 
-__device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, int H, double k_rel,
-                                           double t_abs, int32_t *par, int n_vseams,
-                                           int n_hseams, int64_t i, const float *nrm = nullptr,
-                                           int64_t ld_nrm = 0, int64_t plane_nrm = 0,
-                                           double ccos = 0.0)
+// Seam edges from the raw disparity (covered depth; crease-aware when nrm is
+// set).
+struct DispSeamEdges {
+    const float *D;
+    int64_t ld;
+    double k_rel, t_abs;
+    const float *nrm;
+    int64_t ld_nrm, plane_nrm;
+    double ccos;
+    __device__ __forceinline__ bool operator()(int yp, int xp, int yq, int xq) const
+    {
+        if (!edge(D[(int64_t)yp * ld + xp], D[(int64_t)yq * ld + xq], k_rel, t_abs)) return false;
+        return !nrm || seam_crease(nrm, ld_nrm, plane_nrm, ccos, yp, xp, yq, xq);
+    }
+};
+
+// Seam edges of an explicitly given graph (bits as in BitTileEdges); q is the
+// right or lower pixel of the pair.
+struct BitSeamEdges {
+    const uint8_t *f;
+    int64_t ld;
+    __device__ __forceinline__ bool operator()(int yp, int xp, int yq, int xq) const
+    {
+        const int a = f[(int64_t)yp * ld + xp], b = f[(int64_t)yq * ld + xq];
+        return (a & 1) && (b & 1) && (b & (yq == yp ? 2 : 4));
+    }
+};
+
+// One seam pair under the edges E; `shortcut` skips a pair implied by the
+// previous pair along the seam.
+template <class E>
+__device__ __forceinline__ void merge_pair(const E &edge_at, bool shortcut, int W, int H,
+                                           int32_t *par, int n_vseams, int n_hseams, int64_t i)
 {
     const int64_t nv = (int64_t)n_vseams * H;
-    int p, q;
+    int p, q, yp, xp, yq, xq;
+    bool vert;
     if (i < nv) {
         const int s = (int)(i / H), y = (int)(i - (int64_t)s * H);
         const int x = (s + 1) * kCW;
-        const float *r = D + (int64_t)y * ld;
-        const float dp = r[x - 1], dq = r[x];
-        if (!edge(dp, dq, k_rel, t_abs)) return;
-        if (nrm) {
-            if (!seam_crease(nrm, ld_nrm, plane_nrm, ccos, y, x - 1, y, x)) return;
-        } else if (y % kCH != 0) {
-            const float *u = r - ld;
-            const float up = u[x - 1], uq = u[x];
-            if (edge(up, uq, k_rel, t_abs) && edge(up, dp, k_rel, t_abs) &&
-                edge(uq, dq, k_rel, t_abs))
-                return;
-        }
+        yp = yq = y;
+        xp = x - 1;
+        xq = x;
         p = y * W + x - 1;
         q = p + 1;
+        vert = true;
     } else {
         const int64_t j = i - nv;
         if (j >= (int64_t)n_hseams * W) return;
         const int s = (int)(j / W), x = (int)(j - (int64_t)s * W);
         const int y = (s + 1) * kCH;
-        const float *ra = D + (int64_t)(y - 1) * ld;
-        const float *rb = ra + ld;
-        const float dp = ra[x], dq = rb[x];
-        if (!edge(dp, dq, k_rel, t_abs)) return;
-        if (nrm) {
-            if (!seam_crease(nrm, ld_nrm, plane_nrm, ccos, y - 1, x, y, x)) return;
-        } else if (x % kCW != 0) {
-            const float lp = ra[x - 1], lq = rb[x - 1];
-            if (edge(lp, lq, k_rel, t_abs) && edge(lp, dp, k_rel, t_abs) &&
-                edge(lq, dq, k_rel, t_abs))
-                return;
-        }
+        yp = y - 1;
+        yq = y;
+        xp = xq = x;
         p = (y - 1) * W + x;
         q = p + W;
+        vert = false;
+    }
+    // the forest entries are fetched together with the disparities, so that an
+    // edge costs one round trip before the hook
+    int a = gload(par + p), b = gload(par + q);
+    if (!edge_at(yp, xp, yq, xq)) return;
+    if (shortcut) {
+        if (vert ? yp % kCH != 0 && edge_at(yp - 1, xp, yp - 1, xq) &&
+                       edge_at(yp - 1, xp, yp, xp) && edge_at(yq - 1, xq, yq, xq)
+                 : xp % kCW != 0 && edge_at(yp, xp - 1, yq, xq - 1) &&
+                       edge_at(yp, xp - 1, yp, xp) && edge_at(yq, xq - 1, yq, xq))
+            return;
     }
     // Hook first: the entries of p and q are ancestors of them (their tile
     // roots, or nearer the root after halving), so the larger is hooked under
     // the smaller at once.  If it was still a root the union is done in two
     // round trips; otherwise its old parent, like it an ancestor of one side,
     // is united with the other side by the general path.
-    int a = gload(par + p), b = gload(par + q);
     if (a == b) return;
     if (a < b) { const int t = a; a = b; b = t; }
     const int old = atomicMin(par + a, b);
     if (old == a) return;
     g_union(par, old, b);
+}
+
+__device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, int H, double k_rel,
+                                           double t_abs, int32_t *par, int n_vseams,
+                                           int n_hseams, int64_t i, const float *nrm = nullptr,
+                                           int64_t ld_nrm = 0, int64_t plane_nrm = 0,
+                                           double ccos = 0.0)
+{
+    merge_pair(DispSeamEdges{D, ld, k_rel, t_abs, nrm, ld_nrm, plane_nrm, ccos}, !nrm, W, H, par,
+               n_vseams, n_hseams, i);
+}
+
+__global__ void __launch_bounds__(256)
+k_ccl_merge_edges(const uint8_t *f, int64_t ld, int W, int H, int32_t *par, int n_vseams,
+                  int n_hseams)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    merge_pair(BitSeamEdges{f, ld}, true, W, H, par, n_vseams, n_hseams, i);
 }
 
 __global__ void __launch_bounds__(256)
@@ -353,7 +469,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s)
 
 hipError_t launch_front(const FrontArgs &a, hipStream_t s)
 {
-    const dim3 grid((a.W + kCW - 1) / kCW, (a.H + kCH - 1) / kCH);
+    const dim3 grid(((a.W + kCW - 1) / kCW) * ((a.H + kCH - 1) / kCH));
     if (a.nrm) {
         if (a.rf != 0 || a.dn) return hipErrorInvalidValue;   // crease-aware: forest only
         hipLaunchKernelGGL((k_front<0, true>), grid, dim3(kFrontWaves * 64), 0, s, a);
@@ -422,6 +538,30 @@ hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, 
 
 hipError_t launch_components(const CclArgs &a, hipStream_t s)
 {
+    if (a.edges) {
+        // explicitly given edge graph: its own forest and seam kernels, the
+        // same union-find and flattening
+        FrontArgs f = {};
+        f.W = a.W;
+        f.H = a.H;
+        f.forest = a.parent;
+        f.count = a.count;
+        f.edges = a.edges;
+        f.ld_edges = a.ld;
+        const dim3 grid((a.W + kCW - 1) / kCW, (a.H + kCH - 1) / kCH);
+        hipLaunchKernelGGL(k_front_edges, grid, dim3(kFrontWaves * 64), 0, s, f);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int nv = (int)grid.x - 1, nh = (int)grid.y - 1;
+        const int64_t pairs = (int64_t)nv * a.H + (int64_t)nh * a.W;
+        if (pairs > 0) {
+            hipLaunchKernelGGL(k_ccl_merge_edges, dim3((unsigned)((pairs + 255) / 256)), dim3(256),
+                               0, s, a.edges, a.ld, a.W, a.H, a.parent, nv, nh);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_ccl_flatten, dim3((a.W + 63) / 64, (a.H + 3) / 4), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     FrontArgs f;
     f.D = a.D;
     f.ld = a.ld;

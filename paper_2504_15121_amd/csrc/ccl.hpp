@@ -85,25 +85,71 @@ __device__ __forceinline__ int run_start(unsigned long long starts, int lane)
     return 63 - __clzll(starts & upto);
 }
 
-// Local labelling of one kCW x kCH tile whose validity-coded values sit in LDS
-// at val(ly, lane) (0 = invalid).  Wave `wave` of `nwaves` takes every
-// nwaves-th row.  Horizontal edges come from a 64-bit ballot and give the row
-// runs (first pixel = initial root); vertical edges are united with atomicMin
-// hooking except where the edge at lane-1 already joins the same two runs.
+// Edges of a tile for local_forest, from validity-coded values in LDS at
+// val(ly, lane) (0 = invalid) and the covered-depth predicate;
 // extra(ly_a, x_a, ly_b, x_b) is a further condition on an edge (always true for
-// the covered-depth components).
-// On return (after a barrier) par[] holds a local forest over ly*kCW + lane.
+// the covered-depth components).  Every lane of the wave calls left() together.
 template <class Val, class Extra>
-__device__ __forceinline__ void local_forest(Val val, int *par, unsigned long long *hmask,
-                                             int lane, int wave, int nwaves, double k_rel,
-                                             double t_abs, Extra extra)
+struct DispTileEdges {
+    Val val;
+    Extra extra;
+    double k_rel, t_abs;
+    __device__ __forceinline__ bool ok(int ly, int lane) const { return val(ly, lane) > 0.0f; }
+    // edge between (ly, lane - 1) and (ly, lane)
+    __device__ __forceinline__ bool left(int ly, int lane) const
+    {
+        const float v = val(ly, lane);
+        const float l = __shfl_up(v, 1);
+        return v > 0.0f && lane > 0 && l > 0.0f && joined(v, l, k_rel, t_abs) &&
+               extra(ly, lane > 0 ? lane - 1 : lane, ly, lane);
+    }
+    // edge between (ly - 1, lane) and (ly, lane)
+    __device__ __forceinline__ bool up(int ly, int lane) const
+    {
+        const float v = val(ly, lane), u = val(ly - 1, lane);
+        return v > 0.0f && u > 0.0f && joined(v, u, k_rel, t_abs) && extra(ly - 1, lane, ly, lane);
+    }
+};
+
+template <class Val, class Extra>
+__device__ __forceinline__ DispTileEdges<Val, Extra> disp_edges(Val val, Extra extra,
+                                                                double k_rel, double t_abs)
+{
+    return DispTileEdges<Val, Extra>{val, extra, k_rel, t_abs};
+}
+
+// Edges of a tile given explicitly (the labelling's test hook): per-pixel bits
+// in LDS at f[ly * kCW + lane]: bit 0 present, bit 1 edge to the left
+// neighbour, bit 2 edge to the upper neighbour; an edge needs both pixels.
+struct BitTileEdges {
+    const uint8_t *f;
+    __device__ __forceinline__ bool ok(int ly, int lane) const { return f[ly * kCW + lane] & 1; }
+    __device__ __forceinline__ bool left(int ly, int lane) const
+    {
+        const int c = f[ly * kCW + lane];
+        const int l = __shfl_up(c, 1);
+        return (c & 1) && lane > 0 && (l & 1) && (c & 2);
+    }
+    __device__ __forceinline__ bool up(int ly, int lane) const
+    {
+        const int c = f[ly * kCW + lane], u = f[(ly - 1) * kCW + lane];
+        return (c & 1) && (u & 1) && (c & 4);
+    }
+};
+
+// Local labelling of one kCW x kCH tile with the edges of E.  Wave `wave` of
+// `nwaves` takes every nwaves-th row.  Horizontal edges come from a 64-bit ballot
+// and give the row runs (first pixel = initial root); vertical edges are united
+// with atomicMin hooking except where the edge at lane-1 already joins the same
+// two runs.
+// On return (after a barrier) par[] holds a local forest over ly*kCW + lane.
+template <class Edges>
+__device__ __forceinline__ void local_forest(const Edges &E, int *par, unsigned long long *hmask,
+                                             int lane, int wave, int nwaves)
 {
     for (int ly = wave; ly < kCH; ly += nwaves) {
-        const float v = val(ly, lane);
-        const float left = __shfl_up(v, 1);
-        const bool ok = v > 0.0f;
-        const bool h = ok && lane > 0 && left > 0.0f && joined(v, left, k_rel, t_abs) &&
-                       extra(ly, lane > 0 ? lane - 1 : lane, ly, lane);
+        const bool ok = E.ok(ly, lane);
+        const bool h = E.left(ly, lane);
         const unsigned long long hb = __ballot(h);
         const unsigned long long vb = __ballot(ok);
         par[ly * kCW + lane] = ok ? ly * kCW + run_start(vb & ~hb, lane) : -1;
@@ -111,10 +157,7 @@ __device__ __forceinline__ void local_forest(Val val, int *par, unsigned long lo
     }
     __syncthreads();
     for (int ly = 1 + wave; ly < kCH; ly += nwaves) {
-        const float v = val(ly, lane);
-        const float up = val(ly - 1, lane);
-        const bool e = v > 0.0f && up > 0.0f && joined(v, up, k_rel, t_abs) &&
-                       extra(ly - 1, lane, ly, lane);
+        const bool e = E.up(ly, lane);
         const unsigned long long eb = __ballot(e);
         const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
         if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);

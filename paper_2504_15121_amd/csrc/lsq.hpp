@@ -67,12 +67,12 @@ __device__ __forceinline__ RowMom row_moments(const float *p, int r_rt)
 }
 
 // Row moments of KRUN consecutive centres p[r], p[r+1], ... (windows
-// p[i .. i+2r]) written to ab[i], s[i] in the column-pass format: the first by
+// p[i .. i+2r]) written to ab[i STEP], s[i STEP] in the column-pass format: the first by
 // direct sums, the others by sliding the window one pixel (remove the left
 // tap, add the right one, re-centre).  Every sum is of integers or of float32
 // values in FP64, exact for windows up to 63 and disparities spanning fewer
 // than 2^29 between smallest and largest, so the results equal the direct sums.
-template <int RC, int KRUN>
+template <int RC, int KRUN, int STEP = 1>
 __device__ __forceinline__ void row_moments_run(const float *p, int r_rt, int2 *ab, double2 *s)
 {
     const int r = RC >= 0 ? RC : r_rt;
@@ -104,8 +104,8 @@ __device__ __forceinline__ void row_moments_run(const float *p, int r_rt, int2 *
         const double dvo = (double)vo, dvn = (double)vn;
         s0 = (s0 - dvo) + dvn;
         s1 = ((s1 + (double)r * dvo) + (double)(r + 1) * dvn) - s0;
-        ab[i] = make_int2(n + (sx + kColOff) * 65536, sxx);
-        s[i] = make_double2(s0, s1);
+        ab[i * STEP] = make_int2(n + (sx + kColOff) * 65536, sxx);
+        s[i * STEP] = make_double2(s0, s1);
     }
 }
 

@@ -12,6 +12,18 @@ namespace snx {
 // samples are stored as 0.0f, so "valid" reduces to "> 0".
 __host__ __device__ inline bool valid_disp(float d) { return d > 0.0f && d < INFINITY; }
 
+// XCD-aware tile order.  The dispatcher hands workgroup b of a launch to XCD
+// b % 8 (eight XCDs, each with its own L2); tile indices are assigned so that
+// the workgroups of one XCD cover one contiguous band of the n tiles (row-major
+// over the frame), and a tile's halo is mostly in the L2 its neighbours filled.
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile(int b, int n)
+{
+    const int x = b % kXcds, j = b / kXcds;
+    const int per = n / kXcds, rem = n % kXcds;
+    return x * per + (x < rem ? x : rem) + j;
+}
+
 // Output tile of the stencil kernel: TW columns (one wave's lanes) x th rows.
 constexpr int kTileW = 64;
 constexpr int kBlock = 256;
@@ -100,6 +112,8 @@ struct FrontArgs {
     const float *nrm = nullptr;   // crease-aware components: normal planes (else NULL)
     int64_t ld_nrm = 0, plane_nrm = 0;
     double crease_cos = 0.0;
+    const uint8_t *edges = nullptr;   // explicitly given edge graph (test hook), else NULL
+    int64_t ld_edges = 0;
 };
 hipError_t launch_front(const FrontArgs &a, hipStream_t s);
 hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
@@ -137,6 +151,8 @@ struct CclArgs {
     const float *nrm = nullptr;   // crease-aware components: normal planes (else NULL)
     int64_t ld_nrm = 0, plane_nrm = 0;
     double crease_cos = 0.0;
+    const uint8_t *edges = nullptr;   // explicitly given edge graph (test hook; D unused,
+                                      // ld = its row stride), else NULL
 };
 hipError_t launch_components(const CclArgs &a, hipStream_t s);
 

@@ -1,10 +1,10 @@
 // Adaptive star-fill support (Sec. 3.4, Adaptive Region Estimation) -> slope,
 // A and normal, for one 64 x 16 output tile per 256-thread workgroup.
 //
-// From a valid centre c, rays leave in the 4 (axes) or 8 (axes and diagonals)
-// compass directions -- the directions 2 pi m / M scaled to a unit larger
-// component -- and take c + k e_m, k = 1 .. steps, stopping before the first
-// pixel that is invalid or outside the image or meets the stopping rule:
+// From a valid centre c, rays leave in M = 4 (axes), 8 (axes and diagonals) or
+// 16 directions -- the directions 2 pi m / M scaled to a unit larger component
+// -- and take c + round(k e_m), k = 1 .. steps, stopping before the first pixel
+// that is invalid or outside the image or meets the stopping rule:
 //   CD  D_c (b - a) > k_cd (a b), with a, b the smallest and largest disparity
 //       of c and the ray's pixels so far including the new one (the depth
 //       range f B (1/a - 1/b) exceeds k_cd times the depth of c), binary64;
@@ -18,7 +18,13 @@
 // The rays of the compass directions never share a pixel, so a ray's moments
 // follow from its length n alone (sum k = n(n+1)/2, sum k^2 = n(n+1)(2n+1)/6
 // times the direction's components) plus one exact FP64 sum of k D per ray;
-// the rays of a pixel advance in lock step.
+// the rays of a pixel advance in lock step.  With M = 16 the eight rays in
+// between (angles (2j+1) pi / 8) take c + k A_j + r_k B_j, A_j and B_j unit
+// compass vectors along and across the ray and r_k = round(k tan(pi/8)); their
+// first pixel (r_1 = 0) is the first pixel of the axis ray beside them, taken
+// or refused by that ray under the same test, so the support (the union of the
+// rays' pixels) counts it once: these rays add their pixels from k = 2 on, with
+// integer moment sums and two exact FP64 sums (of k D and of r_k D) each.
 // The tile (validity-coded, halo = steps, + 1 for ST) and, for ST, a byte
 // plane of edge flags sit in LDS.
 #include "lsq.hpp"
@@ -32,11 +38,27 @@ constexpr int kStW = 64, kStH = 16, kStBlock = 256;
 __device__ __forceinline__ constexpr int dir_x(int m) { return m == 0 || m == 1 || m == 7 ? 1 : (m == 2 || m == 6 ? 0 : -1); }
 __device__ __forceinline__ constexpr int dir_y(int m) { return m == 1 || m == 2 || m == 3 ? 1 : (m == 0 || m == 4 ? 0 : -1); }
 
+// the rays between the compass directions (M = 16), j = 0 .. 7 at the angle
+// (2j + 1) pi / 8: the compass vector along the ray (A) and across it (B)
+__device__ __forceinline__ constexpr int odd_ax(int j) { return j == 0 || j == 7 ? 1 : (j == 3 || j == 4 ? -1 : 0); }
+__device__ __forceinline__ constexpr int odd_ay(int j) { return j == 1 || j == 2 ? 1 : (j == 5 || j == 6 ? -1 : 0); }
+__device__ __forceinline__ constexpr int odd_bx(int j) { return j == 1 || j == 6 ? 1 : (j == 2 || j == 5 ? -1 : 0); }
+__device__ __forceinline__ constexpr int odd_by(int j) { return j == 0 || j == 3 ? 1 : (j == 4 || j == 7 ? -1 : 0); }
+
+// round(k tan(pi / 8)) for k = 1 .. 32: k tan(pi/8) is never within 0.015 of a
+// half-integer there, so the binary64 product rounds the same as the exact one
+__device__ __forceinline__ int cross_step(int k)
+{
+    return (int)((double)k * 0.41421356237309503 + 0.5);
+}
+
 template <int M, int STOP>
 __global__ void __launch_bounds__(kStBlock)
 k_star(StarArgs a)
 {
 #pragma clang fp contract(off)
+    constexpr int MC = M < 8 ? M : 8;            // compass rays
+    constexpr int MO = M == 16 ? 8 : 0;          // rays in between
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int s = a.steps;
     const int R = s + (STOP == kStopST ? 1 : 0);     // halo of the value tile
@@ -92,12 +114,12 @@ k_star(StarArgs a)
             // range of the ray so far, as binary64 (exact images of the float
             // values); once a ray has stopped its range is never read again,
             // so it is updated without a select
-            double lo[M], hi[M];
-            double wk[M];
-            int nk[M], pp[M], pe[M];
-            bool alive[M];
+            double lo[MC], hi[MC];
+            double wk[MC];
+            int nk[MC], pp[MC], pe[MC];
+            bool alive[MC];
 #pragma unroll
-            for (int mi = 0; mi < M; ++mi) {
+            for (int mi = 0; mi < MC; ++mi) {
                 lo[mi] = hi[mi] = dc64;
                 wk[mi] = 0.0;
                 nk[mi] = 0;
@@ -105,19 +127,72 @@ k_star(StarArgs a)
                 pe[mi] = ec;
                 alive[mi] = true;
             }
+            // rays in between: range, position, and sums over k >= 2 of 1, k,
+            // k^2, r, r^2, k r (integers) and of k D, r D (binary64, exact)
+            double olo[MO > 0 ? MO : 1], ohi[MO > 0 ? MO : 1];
+            double owk[MO > 0 ? MO : 1], owr[MO > 0 ? MO : 1];
+            int on[MO > 0 ? MO : 1], osk[MO > 0 ? MO : 1], oskk[MO > 0 ? MO : 1];
+            int osr[MO > 0 ? MO : 1], osrr[MO > 0 ? MO : 1], oskr[MO > 0 ? MO : 1];
+            int opp[MO > 0 ? MO : 1], ope[MO > 0 ? MO : 1];
+            bool oalive[MO > 0 ? MO : 1];
+#pragma unroll
+            for (int j = 0; j < MO; ++j) {
+                olo[j] = ohi[j] = dc64;
+                owk[j] = owr[j] = 0.0;
+                on[j] = osk[j] = oskk[j] = osr[j] = osrr[j] = oskr[j] = 0;
+                opp[j] = pc;
+                ope[j] = ec;
+                oalive[j] = true;
+            }
+            int r_prev = 0;
             for (int k = 1; k <= s; ++k) {
                 const double kd = (double)k;
-                float vv[M];
+                float vv[MC];
 #pragma unroll
-                for (int mi = 0; mi < M; ++mi) {
-                    const int m = mi * (8 / M);
+                for (int mi = 0; mi < MC; ++mi) {
+                    const int m = mi * (8 / MC);
                     pp[mi] += dir_y(m) * LW + dir_x(m);
                     vv[mi] = sD[pp[mi]];
                 }
+                const int r = MO ? cross_step(k) : 0;
+                const int dr = r - r_prev;
+                r_prev = r;
+                float ov[MO > 0 ? MO : 1];
+#pragma unroll
+                for (int j = 0; j < MO; ++j) {
+                    opp[j] += odd_ay(j) * LW + odd_ax(j) + dr * (odd_by(j) * LW + odd_bx(j));
+                    ov[j] = sD[opp[j]];
+                }
                 bool any = false;
 #pragma unroll
-                for (int mi = 0; mi < M; ++mi) {
-                    const int m = mi * (8 / M);
+                for (int j = 0; j < MO; ++j) {
+                    const double v = (double)ov[j];
+                    bool ok = oalive[j] && v > 0.0;
+                    if (STOP == kStopCD) {
+                        const double da = fmin(v, olo[j]), db = fmax(v, ohi[j]);
+                        ok = ok && !(dc64 * (db - da) > a.thr * (da * db));
+                        olo[j] = da;
+                        ohi[j] = db;
+                    } else {
+                        ope[j] += odd_ay(j) * EW + odd_ax(j) + dr * (odd_by(j) * EW + odd_bx(j));
+                        ok = ok && !sE[ope[j]];
+                    }
+                    // the first pixel is the neighbouring axis ray's
+                    const bool add = ok && k >= 2;
+                    owk[j] = __builtin_fma(kd, add ? v : 0.0, owk[j]);
+                    owr[j] = __builtin_fma((double)r, add ? v : 0.0, owr[j]);
+                    on[j] += add ? 1 : 0;
+                    osk[j] += add ? k : 0;
+                    oskk[j] += add ? k * k : 0;
+                    osr[j] += add ? r : 0;
+                    osrr[j] += add ? r * r : 0;
+                    oskr[j] += add ? k * r : 0;
+                    oalive[j] = ok;
+                    any = any || ok;
+                }
+#pragma unroll
+                for (int mi = 0; mi < MC; ++mi) {
+                    const int m = mi * (8 / MC);
                     const double v = (double)vv[mi];
                     bool ok = alive[mi] && v > 0.0;
                     if (STOP == kStopCD) {
@@ -141,8 +216,20 @@ k_star(StarArgs a)
             int N = 1, Sx = 0, Sy = 0, Sxx = 0, Sxy = 0, Syy = 0;
             double Rx = 0.0, Ry = 0.0;
 #pragma unroll
-            for (int mi = 0; mi < M; ++mi) {
-                const int m = mi * (8 / M);
+            for (int j = 0; j < MO; ++j) {
+                const int ax = odd_ax(j), ay = odd_ay(j), bx = odd_bx(j), by = odd_by(j);
+                N += on[j];
+                Sx += ax * osk[j] + bx * osr[j];
+                Sy += ay * osk[j] + by * osr[j];
+                Sxx += ax * ax * oskk[j] + bx * bx * osrr[j];
+                Syy += ay * ay * oskk[j] + by * by * osrr[j];
+                Sxy += (ax * by + ay * bx) * oskr[j];
+                Rx += (double)ax * owk[j] + (double)bx * owr[j];
+                Ry += (double)ay * owk[j] + (double)by * owr[j];
+            }
+#pragma unroll
+            for (int mi = 0; mi < MC; ++mi) {
+                const int m = mi * (8 / MC);
                 const int ex = dir_x(m), ey = dir_y(m), n = nk[mi];
                 const int t1 = n * (n + 1) / 2, t2 = n * (n + 1) * (2 * n + 1) / 6;
                 N += n;
@@ -191,7 +278,11 @@ hipError_t launch_star(const StarArgs &a, hipStream_t s)
 {
     const dim3 grid((a.W + kStW - 1) / kStW, (a.H + kStH - 1) / kStH);
     const size_t lds = star_lds_bytes(a.steps, a.stop);
-    if (a.dirs == 8 && a.stop == kStopCD)
+    if (a.dirs == 16 && a.stop == kStopCD)
+        hipLaunchKernelGGL((k_star<16, kStopCD>), grid, dim3(kStBlock), lds, s, a);
+    else if (a.dirs == 16 && a.stop == kStopST)
+        hipLaunchKernelGGL((k_star<16, kStopST>), grid, dim3(kStBlock), lds, s, a);
+    else if (a.dirs == 8 && a.stop == kStopCD)
         hipLaunchKernelGGL((k_star<8, kStopCD>), grid, dim3(kStBlock), lds, s, a);
     else if (a.dirs == 8 && a.stop == kStopST)
         hipLaunchKernelGGL((k_star<8, kStopST>), grid, dim3(kStBlock), lds, s, a);

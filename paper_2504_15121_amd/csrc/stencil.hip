@@ -48,11 +48,21 @@ __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
     return L;
 }
 
+// Threads per workgroup of an instance: 512 (8 waves, 4 resident per SIMD with
+// two workgroups' LDS on a CU) for tiles of 16 rows or more, else 256.
+__host__ __device__ constexpr int stencil_block(int th) { return th >= 16 ? 512 : kBlock; }
+
 // One 64 x th output tile of the stencil.
 template <int RF, int RG, int TH>
 __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int by,
                                              unsigned char *smem)
 {
+    constexpr int NB = stencil_block(TH);        // threads
+    // Outputs: thread (wave w, lane x) owns runs of RPT consecutive rows of
+    // column x, rows RPT w + kRowStep j .. + RPT - 1, j = 0, 1, ...: the column
+    // sums of a run's first row are direct, the others slide down one row
+    constexpr int RPT = TH > 0 && TH * 64 / NB > 2 ? TH * 64 / NB : 2;
+    constexpr int kRowStep = RPT * (NB / 64);   // rows covered by one round of runs
     const int rf = RF >= 0 ? RF : a.rf;
     const int rg = RG >= 0 ? RG : a.rg;
     const int th = TH > 0 ? TH : a.th;
@@ -70,36 +80,34 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     // ---- A: validity-coded input tile with halo R --------------------------
     // Labels (or the label forest) of this thread's outputs are fetched first so
     // their latency overlaps the LDS phases.
-    // Outputs: thread (wave w, lane x) owns the vertical pairs of rows
-    // (2w + 8j, 2w + 8j + 1) of column x, j = 0, 1, ...
-    const int px_col = tid & 63, px_row = 2 * (tid >> 6);
-    constexpr int kPairs = TH > 0 ? (TH + 7) / 8 : 1;
-    int32_t lab0[2 * kPairs], labr[2 * kPairs];   // forest entries, their roots
+    const int px_col = tid & 63, px_row = RPT * (tid >> 6);
+    constexpr int kPairs = TH > 0 ? (TH + kRowStep - 1) / kRowStep : 1;
+    int32_t lab0[RPT * kPairs], labr[RPT * kPairs];   // forest entries, their roots
     if (TH > 0) {
 #pragma unroll
         for (int j = 0; j < kPairs; ++j)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ty = px_row + 8 * j + h;
+            for (int h = 0; h < RPT; ++h) {
+                const int ty = px_row + kRowStep * j + h;
                 const int gx = x0 + px_col, gy = y0 + ty;
                 int32_t v = -1;
                 if (rg > 0 && ty < th && gx < a.W && gy < a.H) {
                     if (a.forest) v = a.forest[gy * a.W + gx];
                     else if (a.labels) v = a.labels[(int64_t)gy * a.ld_lab + gx];
                 }
-                lab0[2 * j + h] = v;
-                labr[2 * j + h] = v;
+                lab0[RPT * j + h] = v;
+                labr[RPT * j + h] = v;
             }
     }
     if (RF >= 0 && RG >= 0 && TH > 0) {
         // static tile: issue every load before the first wait
         constexpr int sR = (RF > 0 ? RF : 0) + (RG > 0 ? RG : 0);
         constexpr int sW = kTileW + 2 * sR, sH = (TH > 0 ? TH : 1) + 2 * sR;
-        constexpr int NT = sW * sH, NL = (NT + kBlock - 1) / kBlock;
+        constexpr int NT = sW * sH, NL = (NT + NB - 1) / NB;
         float v[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int e = tid + k * kBlock;
+            const int e = tid + k * NB;
             const int ly = e / sW, lx = e - ly * sW;
             const int gy = y0 - sR + ly, gx = x0 - sR + lx;
             v[k] = 0.0f;
@@ -112,11 +120,11 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
             bool again = true;
             while (again) {
                 again = false;
-                int32_t nx[2 * kPairs];
+                int32_t nx[RPT * kPairs];
 #pragma unroll
-                for (int k = 0; k < 2 * kPairs; ++k) nx[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
+                for (int k = 0; k < RPT * kPairs; ++k) nx[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
 #pragma unroll
-                for (int k = 0; k < 2 * kPairs; ++k)
+                for (int k = 0; k < RPT * kPairs; ++k)
                     if (nx[k] != labr[k]) {
                         labr[k] = nx[k];
                         again = true;
@@ -125,11 +133,11 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int e = tid + k * kBlock;
+            const int e = tid + k * NB;
             if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
         }
     } else {
-        for (int e = tid; e < L.inH * L.inW; e += kBlock) {
+        for (int e = tid; e < L.inH * L.inW; e += NB) {
             const int ly = e / L.inW, lx = e - ly * L.inW;
             const int gy = y0 - R + ly, gx = x0 - R + lx;
             float v = 0.0f;
@@ -145,7 +153,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     // ---- B: filter into sDt (validity-coded) and the optional plane ---------
     if (rf > 0) {
         if (rf >= 2) {
-            for (int e = tid; e < L.inH * L.dtW; e += kBlock) {
+            for (int e = tid; e < L.inH * L.dtW; e += NB) {
                 const int ly = e / L.dtW, j = e - ly * L.dtW;
                 const RowMom m = row_moments<RF>(sIn + ly * L.inW + j, rf);
                 sAB[e] = make_int2(m.a, m.b);
@@ -153,7 +161,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
             }
             __syncthreads();
         }
-        for (int e = tid; e < L.dtH * L.dtW; e += kBlock) {
+        for (int e = tid; e < L.dtH * L.dtW; e += NB) {
             const int ty = e / L.dtW, j = e - ty * L.dtW;
             const float Dc = sIn[(ty + rf) * L.inW + j + rf];
             float outv = __builtin_nanf("");
@@ -173,7 +181,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
         }
         __syncthreads();
     } else if (a.dn) {
-        for (int e = tid; e < th * kTileW; e += kBlock) {
+        for (int e = tid; e < th * kTileW; e += NB) {
             const int ty = e >> 6, tx = e & 63;
             const int gx = x0 + tx, gy = y0 + ty;
             if (gx < a.W && gy < a.H) {
@@ -190,27 +198,31 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     // and row.
     __shared__ int s_roots;
     if (tid == 0) s_roots = 0;
-    // row moments: runs of 4 consecutive centres per thread (sliding window)
-    constexpr int kRun = 4;
-    for (int e = tid; e < L.dtH * (kTileW / kRun); e += kBlock) {
-        const int ly = e / (kTileW / kRun), tx0 = (e - ly * (kTileW / kRun)) * kRun;
-        row_moments_run<RG, kRun>(sDt + ly * L.dtW + tx0, rg, sAB + ly * kTileW + tx0,
-                                  sS + ly * kTileW + tx0);
+    // row moments: runs of 4 consecutive centres per thread (sliding window).
+    // Within a row, the moments of column x sit at slot (x % 4) * 16 + x / 4, so
+    // at every step of the runs the lanes of a wave write consecutive slots (no
+    // LDS bank conflicts), and a row's 64 columns still fill its 64 slots.
+    constexpr int kRun = 4, kRuns = kTileW / kRun;
+    for (int e = tid; e < L.dtH * kRuns; e += NB) {
+        const int ly = e / kRuns, run = e - ly * kRuns;
+        row_moments_run<RG, kRun, kRuns>(sDt + ly * L.dtW + run * kRun, rg,
+                                         sAB + ly * kTileW + run, sS + ly * kTileW + run);
     }
     __syncthreads();
-    // column moments: the first row of a pair by direct sums, the second by
-    // sliding the window down one row.  The pairs are unrolled for the static
-    // tile heights so that the per-pair label registers are indexed statically.
+    // column moments: the first row of a run by direct sums, the others by
+    // sliding the window down one row.  The runs are unrolled for the static
+    // tile heights so that the per-run label registers are indexed statically.
     auto pair = [&](int j) {
-        const int ty0 = px_row + 8 * j, tx = px_col;
-        const int eo = ty0 * kTileW + tx;
+        const int ty0 = px_row + kRowStep * j, tx = px_col;
+        const int eo = ty0 * kTileW + (tx % kRun) * kRuns + tx / kRun;
         ColMom m = col_moments<RG, true>(sAB + eo, sS + eo, kTileW, rg);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < RPT; ++h) {
             const int ty = ty0 + h;
-            if (h == 1) {
+            if (h >= 1) {
                 if (ty >= th) break;
-                m = col_slide(m, sAB + eo, sS + eo, kTileW, rg);
+                m = col_slide(m, sAB + eo + (h - 1) * kTileW, sS + eo + (h - 1) * kTileW, kTileW,
+                              rg);
             }
             const int gx = x0 + tx, gy = y0 + ty;
             const bool in = gx < a.W && gy < a.H;
@@ -228,7 +240,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
             bool root = false;
             int32_t first = -1;
             if (in) {
-                if (TH > 0) first = lab0[2 * j + h];
+                if (TH > 0) first = lab0[RPT * j + h];
                 else if (a.forest) first = a.forest[gy * a.W + gx];
                 else if (a.labels) first = a.labels[(int64_t)gy * a.ld_lab + gx];
             }
@@ -236,7 +248,7 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
                 const int x = gy * a.W + gx;
                 const int p = first;
                 if (p >= 0) {
-                    lab = (RF >= 0 && RG >= 0 && TH > 0) ? labr[2 * j + h] : flat_find(a.forest, p);
+                    lab = (RF >= 0 && RG >= 0 && TH > 0) ? labr[RPT * j + h] : flat_find(a.forest, p);
                     root = lab == x;
                     if (a.labels == a.forest) {
                         if (lab != p) a.forest[x] = lab;
@@ -271,9 +283,9 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     if (TH > 0) {
 #pragma unroll
         for (int j = 0; j < kPairs; ++j)
-            if (px_row + 8 * j < th) pair(j);
+            if (px_row + kRowStep * j < th) pair(j);
     } else {
-        for (int j = 0; px_row + 8 * j < th; ++j) pair(j);
+        for (int j = 0; px_row + kRowStep * j < th; ++j) pair(j);
     }
     if (a.count) {
         __syncthreads();
@@ -282,16 +294,19 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
 }
 
 template <int RF, int RG, int TH>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(stencil_block(TH))
 k_stencil(StencilArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    stencil_tile<RF, RG, TH>(a, blockIdx.x, blockIdx.y, smem);
+    const int th = TH > 0 ? TH : a.th;
+    const int tx = (a.W + kTileW - 1) / kTileW, ty = (a.H + th - 1) / th;
+    const int t = xcd_tile(blockIdx.x, tx * ty);
+    stencil_tile<RF, RG, TH>(a, t % tx, t / tx, smem);
 }
 
 // Persistent back stage over the (frame, tile) work list of a batch.
 template <int RG, int TH>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(stencil_block(TH))
 k_back_batch(const BatchFrame *frames, const int *tile_off, const int *tile_frame, int n,
              int *counter)
 {
@@ -376,7 +391,8 @@ hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, cons
 {
     for (const BatchInst &i : kBatchInst)
         if (i.rg == rg && i.th == th) {
-            hipLaunchKernelGGL(i.fn, dim3(grid), dim3(kBlock), stencil_lds_bytes(0, rg, th), s,
+            hipLaunchKernelGGL(i.fn, dim3(grid), dim3(stencil_block(th)),
+                               stencil_lds_bytes(0, rg, th), s,
                                frames, tile_off, tile_frame, n, counter);
             return hipGetLastError();
         }
@@ -410,11 +426,15 @@ hipError_t launch_stencil(const StencilArgs &a, hipStream_t s)
 {
     const size_t lds = stencil_lds_bytes(a.rf, a.rg, a.th);
     if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-    dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + a.th - 1) / a.th);
+    const dim3 grid(((a.W + kTileW - 1) / kTileW) * ((a.H + a.th - 1) / a.th));
     KernelFn fn = &k_stencil<-1, -1, 0>;
+    int nb = kBlock;
     for (const Inst &i : kInst)
-        if (i.rf == a.rf && i.rg == a.rg && i.th == a.th) fn = i.fn;
-    hipLaunchKernelGGL(fn, grid, dim3(kBlock), lds, s, a);
+        if (i.rf == a.rf && i.rg == a.rg && i.th == a.th) {
+            fn = i.fn;
+            nb = stencil_block(i.th);
+        }
+    hipLaunchKernelGGL(fn, grid, dim3(nb), lds, s, a);
     return hipGetLastError();
 }
 

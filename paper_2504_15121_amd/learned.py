@@ -5,23 +5,21 @@ snx_cnn_denoise; this module only owns device buffers, builds batches from the
 seeded crop generator, steps the learning-rate schedule and reads/writes
 checkpoints.
 
-Checkpoint: a .npz file with the FP32 parameters, the Adam moments, the step
-count, the seed and a CRC32 of the parameter and moment bytes.  It is written to
-a temporary file and renamed, so a checkpoint on disk is always complete;
-loading checks the version and the CRC.
+Checkpoint: the library's model file (snx_model_save / snx_model_load: FP32
+parameters, Adam moments, step, seed, training window and fidelity weight, a
+version and a CRC-32), written to a temporary file and renamed, so a checkpoint
+on disk is always complete; loading checks the version, the size and the CRC.
 """
 from __future__ import annotations
 
 import os
-import zlib
 
 import numpy as np
 
 from . import _lib
 
-CKPT_VERSION = 1
 MODEL_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models")
-DEFAULT_MODEL = os.path.join(MODEL_DIR, "denoiser_ng9.npz")
+DEFAULT_MODEL = os.path.join(MODEL_DIR, "denoiser_ng9.snxm")
 LAYERS = [(2, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1)]
 
 
@@ -132,21 +130,15 @@ class Trainer:
         return _lib.cnn_model(self.params, self.packed, workspace)
 
     # -------------------------------------------------------------- checkpoint
-    def state(self):
-        p = self.params.cpu().numpy()
-        m = self.m.cpu().numpy()
-        v = self.v.cpu().numpy()
-        crc = zlib.crc32(p.tobytes() + m.tobytes() + v.tobytes())
-        return dict(version=CKPT_VERSION, params=p, m=m, v=v, step=self.step, seed=self.seed,
-                    normal_window=self.normal_window, fidelity=self.fidelity, crc=crc)
-
     def save(self, path):
-        tmp = path + ".tmp.npz"
-        np.savez(tmp, **self.state())
-        os.replace(tmp, path)
+        _lib.model_save(path, self.params.cpu().numpy(), self.m.cpu().numpy(),
+                        self.v.cpu().numpy(), step=self.step, normal_window=self.normal_window,
+                        seed=self.seed, fidelity=self.fidelity)
 
     def load(self, path):
         st = load_checkpoint(path)
+        if st["m"] is None:
+            raise CheckpointError(f"{path}: no Adam state to resume from")
         self.params.copy_(self.torch.from_numpy(st["params"]))
         self.m.copy_(self.torch.from_numpy(st["m"]))
         self.v.copy_(self.torch.from_numpy(st["v"]))
@@ -160,17 +152,12 @@ class CheckpointError(ValueError):
 
 
 def load_checkpoint(path):
-    with np.load(path, allow_pickle=False) as z:
-        st = {k: z[k] for k in z.files}
-    if int(st.get("version", -1)) != CKPT_VERSION:
-        raise CheckpointError(f"{path}: unsupported checkpoint version")
-    p, m, v = (np.ascontiguousarray(st[k], np.float32) for k in ("params", "m", "v"))
-    if p.size != _lib.snx_cnn_param_count() or m.size != p.size or v.size != p.size:
-        raise CheckpointError(f"{path}: wrong parameter count")
-    if zlib.crc32(p.tobytes() + m.tobytes() + v.tobytes()) != int(st["crc"]):
-        raise CheckpointError(f"{path}: CRC mismatch")
-    st.update(params=p, m=m, v=v)
-    return st
+    """The model file's contents (see _lib.model_load); CheckpointError if the
+    file is missing, corrupt or of another version."""
+    try:
+        return _lib.model_load(path)
+    except _lib.SnxError as e:
+        raise CheckpointError(str(e)) from None
 
 
 # ------------------------------------------------------------------ training CLI

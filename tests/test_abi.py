@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 28
+    assert len(names) == 35
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -140,7 +140,7 @@ def test_star_validation(lib):
         return lib.snx_affine_normals_star(FAKE, 64, w, h, C.byref(c) if c is not None else None,
                                            C.byref(p) if p is not None else None, aff, nrm, out,
                                            None)
-    assert call(snx_star_params(16, 10, 0, 0, 0.05)) == 2        # unsupported direction count
+    assert call(snx_star_params(12, 10, 0, 0, 0.05)) == 2        # unsupported direction count
     assert call(snx_star_params(0, 10, 0, 0, 0.05)) == 1
     assert call(snx_star_params(8, 0, 0, 0, 0.05)) == 1
     assert call(snx_star_params(8, 33, 0, 0, 0.05)) == 1
@@ -252,3 +252,104 @@ def test_plan_validation(lib):
     assert lib.snx_plan_create(C.cast(bad, C.c_void_p), 1, C.byref(_dn()), C.byref(nr),
                                C.byref(cp), C.byref(out)) == 1                  # stride < width
     assert lib.snx_plan_run(None, None) == 1
+
+
+# ---------------------------------------------------------------- model files
+def _model_file(tmp_path, moments=True, seed=3):
+    import numpy as np
+    from paper_2504_15121_amd import _lib
+    n = _lib.snx_cnn_param_count()
+    rng = np.random.default_rng(seed)
+    p, m, v = (rng.normal(0, 1, n).astype(np.float32) for _ in range(3))
+    path = str(tmp_path / "m.snxm")
+    _lib.model_save(path, p, m if moments else None, v if moments else None, step=1234,
+                    normal_window=9, seed=seed, fidelity=0.25)
+    return path, p, m, v
+
+
+@pytest.mark.parametrize("moments", [True, False])
+def test_model_file_round_trip_and_layout(lib, tmp_path, moments):
+    import struct
+    import zlib
+    import numpy as np
+    from paper_2504_15121_amd import _lib
+    path, p, m, v = _model_file(tmp_path, moments)
+    raw = open(path, "rb").read()
+    n = _lib.snx_cnn_param_count()
+    assert len(raw) == 40 + (3 if moments else 1) * 4 * n + 4
+    magic, ver, cnt, flags, step, ng, seed, fid, res = struct.unpack("<4sIIIqiifI", raw[:40])
+    assert (magic, ver, cnt, flags, step, ng, seed, res) == (b"SNXM", 1, n, int(moments), 1234,
+                                                             9, 3, 0)
+    assert fid == np.float32(0.25)
+    # the library's CRC-32 is zlib's
+    assert struct.unpack("<I", raw[-4:])[0] == zlib.crc32(raw[:-4])
+    assert np.array_equal(np.frombuffer(raw[40:40 + 4 * n], np.float32), p)
+    st = _lib.model_load(path)
+    assert np.array_equal(st["params"], p)
+    if moments:
+        assert np.array_equal(st["m"], m) and np.array_equal(st["v"], v)
+    else:
+        assert st["m"] is None and st["v"] is None
+    assert (st["step"], st["normal_window"], st["seed"]) == (1234, 9, 3)
+    assert not os.path.exists(path + ".tmp")       # written to .tmp, then renamed
+
+
+def _status_of_load(lib, path):
+    h = C.c_void_p(0x1234)
+    st = lib.snx_model_load(os.fsencode(path), C.byref(h))
+    if st == 0:
+        lib.snx_model_destroy(h)
+    else:
+        assert h.value is None                     # no model on failure
+    return st
+
+
+def test_model_file_corruption_is_refused(lib, tmp_path):
+    import struct
+    import zlib
+    path, _, _, _ = _model_file(tmp_path)
+    raw = open(path, "rb").read()
+    bad = str(tmp_path / "bad.snxm")
+
+    def status(data):
+        open(bad, "wb").write(data)
+        return _status_of_load(lib, bad)
+
+    assert status(raw) == 0
+    for cut in (0, 3, 39, 40, 44, len(raw) // 2, len(raw) - 5, len(raw) - 1):
+        assert status(raw[:cut]) == 5, cut                       # truncated
+    assert status(raw + b"\0") == 5                               # trailing bytes
+    flip = bytearray(raw)
+    flip[40 + 1000] ^= 0x10
+    assert status(bytes(flip)) == 5                               # CRC
+    assert b"CRC" in lib.snx_last_error()
+    assert status(b"SNXX" + raw[4:]) == 5                         # magic
+
+    def with_header(off, fmt, val):
+        b = bytearray(raw)
+        struct.pack_into(fmt, b, off, val)
+        struct.pack_into("<I", b, len(b) - 4, zlib.crc32(bytes(b[:-4])))
+        return bytes(b)
+
+    assert status(with_header(4, "<I", 2)) == 5                   # version
+    assert status(with_header(8, "<I", 100)) == 5                 # parameter count
+    assert status(with_header(12, "<I", 2)) == 5                  # unknown flag
+    assert status(with_header(12, "<I", 0)) == 5                  # size disagrees with flags
+    assert _status_of_load(lib, str(tmp_path / "missing.snxm")) == 6
+    assert lib.snx_model_save(None, os.fsencode(bad)) == 1
+
+
+def test_model_read_without_moments(lib, tmp_path):
+    path, _, _, _ = _model_file(tmp_path, moments=False)
+    h = C.c_void_p()
+    assert lib.snx_model_load(os.fsencode(path), C.byref(h)) == 0
+    buf = (C.c_float * 64)()
+    assert lib.snx_model_read(h, None, buf, buf, None) == 5
+    assert lib.snx_model_destroy(h) == 0
+    assert lib.snx_model_destroy(None) == 0
+
+
+def test_committed_model_loads():
+    from paper_2504_15121_amd import learned
+    st = learned.load_checkpoint(learned.DEFAULT_MODEL)
+    assert st["m"] is not None and st["step"] > 0 and st["normal_window"] == 9

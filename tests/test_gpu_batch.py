@@ -142,3 +142,104 @@ def test_plan_rejects_incomplete_model():
     with pytest.raises(snx.SnxError) as ei:
         snx.Plan(frames, cnn=snx_cnn_model(P.data_ptr(), None, None, 0))   # no packed weights
     assert ei.value.status == 5
+
+
+# ---------------------------------------------------------------------------
+# Batch plans against the FP64 oracle, stage by stage (not only against
+# snx_pipeline, which shares the plan's kernels)
+def _cam32(cam):
+    f = lambda x: float(np.float32(x))
+    return scenes.Camera(f(cam.fx), f(cam.fy), f(cam.baseline), f(cam.u0), f(cam.v0))
+
+
+def _oracle_frames(with_big):
+    """Frames of the uneven-batch recipe (640..2880 x 480..1988, planes and
+    spheres, disparities up to 280 px): optionally one at the recipe's largest
+    size, 2880x1988, and five shrunk ones of other seeds."""
+    specs = scenes.uneven_batch_specs(5, seed=3001, size_scale=0.3)
+    if with_big:
+        specs = [dict(scenes.uneven_batch_specs(1, seed=3000)[0], width=2880, height=1988)] + specs
+    return [scenes.uneven_frame(sp) for sp in specs]
+
+
+@pytest.mark.parametrize("filter_window,normal_window", [(3, 9), (1, 15)])
+def test_plan_matches_oracle_stagewise(oracle, filter_window, normal_window):
+    from tests.stagewise import check_records
+    snx = _snx()
+    # the 2880x1988 frame runs with the headline windows only
+    scs = _oracle_frames(with_big=normal_window == 9)
+    print(f"case plan vs oracle f{filter_window} g{normal_window} "
+          f"{[sc.disp.shape[::-1] for sc in scs]}", flush=True)
+    frames = [_alloc(sc, label_pad=(3 if k % 2 else 0)) for k, sc in enumerate(scs)]
+    plan = snx.Plan(frames, filter_window=filter_window, normal_window=normal_window)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.run(st)
+        plan.run(st)            # a graph replay, after the capturing run
+    st.synchronize()
+    for i, (sc, f) in enumerate(zip(scs, frames)):
+        print(f"  frame {i} {sc.disp.shape[::-1]}", flush=True)
+        ang = check_records(oracle, sc.disp, _cam32(sc.cam), normal_window,
+                            f["disp_dn"].cpu().numpy(), f["labels"].cpu().numpy(),
+                            int(f["num_components"].item()), f["points"].cpu().numpy(),
+                            nf=filter_window)
+        print(f"  max normal angle {ang:.2e} rad", flush=True)
+    plan.close()
+
+
+def test_plan_learned_road_frames_match_oracle(oracle):
+    """The learned filter through a plan on full 2048x1024 road frames with the
+    committed weights: D~ at >= 1000 sampled pixels against the BF16-emulating
+    network oracle on the crop the pixel depends on (six 3x3 layers and the 3x3
+    mu: radius 7, cut at the border), with the forward tolerances of the
+    single-frame tests; every later stage over the whole frame against the
+    oracle run on the plan's own D~."""
+    from oracle import cnn_oracle as cnn
+    from paper_2504_15121_amd import learned
+    from tests.stagewise import check_records
+    snx = _snx()
+    print("case plan learned road 2048x1024 vs oracle", flush=True)
+    flat = learned.load_checkpoint(learned.DEFAULT_MODEL)["params"].astype(np.float32)
+    p32, o = [], 0
+    for ci, co in cnn.LAYERS:
+        w = flat[o:o + co * ci * 9].astype(np.float64).reshape(co, ci, 3, 3)
+        o += co * ci * 9
+        p32.append((w, flat[o:o + co].astype(np.float64)))
+        o += co
+    P = torch.from_numpy(flat).to(DEV)
+    packed = torch.empty(snx.snx_cnn_packed_bytes() // 2, dtype=torch.int16, device=DEV)
+    snx.snx_cnn_pack(P, packed)
+    ws = torch.empty(snx.snx_cnn_workspace_size(64, 64, 1, 0), dtype=torch.uint8, device=DEV)
+    model = snx.cnn_model(P, packed, ws)
+    scs = [scenes.road_scene(seed=5400 + i) for i in range(2)]
+    scs.append(scenes.road_scene(width=333, height=170, f=370.0, seed=5402))
+    frames = [_alloc(sc, label_pad=(5 if k == 1 else 0)) for k, sc in enumerate(scs)]
+    plan = snx.Plan(frames, normal_window=9, cnn=model)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan.run(st)
+    st.synchronize()
+    rng = np.random.default_rng(12)
+    for i, (sc, f) in enumerate(zip(scs, frames)):
+        H, W = sc.disp.shape
+        dn = f["disp_dn"].cpu().numpy()
+        n = 1000 if i < 2 else 200
+        pix = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (23, 24), (24, 23), (H // 2, min(479, W - 1))]
+        pix += [(int(v), int(u)) for v, u in zip(rng.integers(0, H, n), rng.integers(0, W, n))]
+        errs = []
+        for v, u in pix:
+            v0, v1, u0, u1 = max(0, v - 8), min(H, v + 9), max(0, u - 8), min(W, u + 9)
+            ref = cnn.forward(sc.disp[v0:v1, u0:u1].astype(np.float64), p32,
+                              emulate_bf16=True)[v - v0, u - u0]
+            if np.isnan(ref):
+                assert np.isnan(dn[v, u]), (i, v, u)
+                continue
+            errs.append(abs(float(dn[v, u]) - float(ref)))
+        errs = np.array(errs)
+        print(f"  frame {i} {W}x{H}: D~ at {errs.size} pixels, max {errs.max():.3e} "
+              f"mean {errs.mean():.3e} p99 {np.quantile(errs, 0.99):.3e}", flush=True)
+        assert errs.max() <= 0.05 and errs.mean() <= 4e-4 and np.quantile(errs, 0.99) <= 0.01
+        ang = check_records(oracle, sc.disp, _cam32(sc.cam), 9, dn, f["labels"].cpu().numpy(),
+                            int(f["num_components"].item()), f["points"].cpu().numpy())
+        print(f"  max normal angle {ang:.2e} rad", flush=True)
+    plan.close()

@@ -12,9 +12,18 @@ Tolerances:
             max 0.05, mean 4e-4, p99 0.01.
   loss      FP64 head on the GPU's own D~ (the same kernels as the denoising
             call, so bit-identical): relative 1e-9 against the oracle head.
-  gradients the GPU rounds each layer's output gradient to bfloat16 for the MFMA
-            backward-data pass (2^-9 relative per layer); per layer the gradient
-            must have cosine >= 0.995 with the oracle's and relative error <= 0.1.
+  gradients the oracle's backward is FP64 throughout; the GPU rounds dL/dy and
+            every backward-data result to bfloat16 and sums weight gradients in
+            FP32 (tests/cnn_replay.py lists the rounding points), and its
+            forward activations differ from the oracle's where an FP32 summation
+            order flips a bfloat16 rounding.  On the test's own inputs the
+            replay of those roundings with FP64 sums (R64) and with FP32 sums in
+            random orders, forward and backward (R32, three orders), is
+            computed; per layer the GPU must satisfy
+              |g - oracle| / |oracle| <= 3 (|R64 - oracle| + max |R32 - R64|) / |oracle| + 1e-7
+            (which also bounds 1 - cos by half its square; the rounding effect is 1e-3 .. 4e-3 relative on the first layers
+            and 1e-8 on the last, the order spread up to 8e-3 and 6e-4:
+            test_oracle_cnn.py::test_backward_rounding_replay).
 """
 import numpy as np
 import pytest
@@ -149,19 +158,31 @@ def test_loss_and_gradients_match_oracle(fid):
     if fid:
         assert abs(gl[3] - Lf) <= 1e-9 * abs(Lf), (gl[3], Lf)
     assert abs(gl[0] - Lref) <= 1e-9 * abs(Lref), (gl[0], Lref)
+    from tests import cnn_replay
     gref = np.zeros_like(gg)
+    r64 = np.zeros_like(gg)
+    r32 = [np.zeros_like(gg) for _ in range(3)]
     for b, (c, (L, u, dDt)) in enumerate(zip(crops, parts)):
         up = dDt * u / Ntot + (fid * dF[b] if fid else 0.0)
         gr = cnn.backward(c.disp, p32, up, emulate_bf16=True)
         gref += np.concatenate([np.concatenate([w.ravel(), b_.ravel()]) for w, b_ in gr])
+        r64 += cnn_replay.flat(cnn_replay.replay(c.disp, p32, up))
+        for sd in range(3):
+            r32[sd] += cnn_replay.flat(cnn_replay.replay(c.disp, p32, up,
+                                                         order=np.random.default_rng(10 * b + sd)))
+    nrm = np.linalg.norm
     off = 0
     for k, (w, b) in enumerate(p32):
         n = w.size + b.size
-        a, r = gg[off:off + n], gref[off:off + n]
-        cos = a @ r / (np.linalg.norm(a) * np.linalg.norm(r))
-        rel = np.linalg.norm(a - r) / np.linalg.norm(r)
-        print(f"layer {k + 1}: cos {cos:.6f} rel {rel:.3e}")
-        assert cos >= 0.995 and rel <= 0.1, (k, cos, rel)
+        a, r, q = gg[off:off + n], gref[off:off + n], r64[off:off + n]
+        spread = max(nrm(x[off:off + n] - q) for x in r32)
+        cos = a @ r / (nrm(a) * nrm(r))
+        rel = nrm(a - r) / nrm(r)
+        # 1 - cos <= rel^2 / 2, so the relative bound also bounds the direction
+        rel_bound = 3.0 * (nrm(q - r) + spread) / nrm(r) + 1e-7
+        print(f"layer {k + 1}: cos {cos:.9f} rel {rel:.3e} (bound {rel_bound:.3e}); "
+              f"vs replay rel {nrm(a - q) / nrm(q):.3e}, order spread {spread / nrm(q):.3e}")
+        assert rel <= rel_bound, (k, rel, rel_bound)
         off += n
 
 
@@ -235,7 +256,9 @@ def test_forward_full_frame_sampled():
     size) with the committed weights, checked at sampled pixels: an output
     depends only on the disparity within 7 px (six 3x3 layers and the 3x3 mu),
     so the oracle run on a 17x17 crop around a pixel (cut at the image border
-    where the pixel is near it) gives that pixel's exact reference."""
+    where the pixel is near it) gives that pixel's exact reference.  The oracle
+    rounds to bfloat16 at the GPU's points; over >= 1000 pixels the forward
+    tolerances of test_forward_matches_oracle apply."""
     from oracle import cnn_oracle as cnn
     from paper_2504_15121_amd import learned
     snx = _snx()
@@ -261,15 +284,50 @@ def test_forward_full_frame_sampled():
     rng = np.random.default_rng(11)
     pts = [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (23, 24), (24, 23), (47, 48),
            (H // 2, 24 * 40), (H // 2, 24 * 40 - 1), (H - 2, 1000), (5, W - 6)]
-    pts += [(int(v), int(u)) for v, u in zip(rng.integers(0, H, 37), rng.integers(0, W, 37))]
+    pts += [(int(v), int(u)) for v, u in zip(rng.integers(0, H, 1200), rng.integers(0, W, 1200))]
     errs = []
     for v, u in pts:
         v0, v1, u0, u1 = max(0, v - 8), min(H, v + 9), max(0, u - 8), min(W, u + 9)
-        ref = cnn.forward(sc.disp[v0:v1, u0:u1].astype(np.float64), p32)[v - v0, u - u0]
+        ref = cnn.forward(sc.disp[v0:v1, u0:u1].astype(np.float64), p32,
+                          emulate_bf16=True)[v - v0, u - u0]
         if np.isnan(ref):
             assert np.isnan(g[v, u]), (v, u)
             continue
         errs.append(abs(float(g[v, u]) - float(ref)))
     errs = np.array(errs)
-    assert errs.size > 30
-    assert errs.max() <= 0.05 and errs.mean() <= 4e-3, (errs.max(), errs.mean())
+    print(f"{errs.size} pixels: max {errs.max():.3e} mean {errs.mean():.3e} "
+          f"p99 {np.quantile(errs, 0.99):.3e}", flush=True)
+    assert errs.size >= 1000
+    assert errs.max() <= 0.05 and errs.mean() <= 4e-4 and np.quantile(errs, 0.99) <= 0.01, \
+        (errs.max(), errs.mean(), np.quantile(errs, 0.99))
+
+
+def test_model_file_bind_matches_explicit_buffers():
+    """snx_model_load + snx_model_bind (the library's own device copies and
+    packing) give the same D~ as parameters uploaded and packed by the caller."""
+    import ctypes as C
+    import os
+    from paper_2504_15121_amd import _lib, learned
+    snx = _snx()
+    print("case model file bind", flush=True)
+    lib = _lib.load()
+    sc = scenes.road_scene(width=300, height=170, f=330.0, seed=77)
+    H, W = sc.disp.shape
+    d = torch.from_numpy(sc.disp).to(DEV)
+    h = C.c_void_p()
+    assert lib.snx_model_load(os.fsencode(learned.DEFAULT_MODEL), C.byref(h)) == 0
+    view = _lib.snx_cnn_model()
+    assert lib.snx_model_bind(h, W, H, None, C.byref(view)) == 0
+    out_a = torch.empty((H, W), device=DEV)
+    snx.snx_cnn_denoise(d, view, out_a)
+    flat = learned.load_checkpoint(learned.DEFAULT_MODEL)["params"].astype(np.float32)
+    P, packed = _packed(snx, flat)
+    ws = torch.empty(snx.snx_cnn_workspace_size(W, H, 1, 0), dtype=torch.uint8, device=DEV)
+    out_b = torch.empty((H, W), device=DEV)
+    snx.snx_cnn_denoise(d, snx.cnn_model(P, packed, ws), out_b)
+    torch.cuda.synchronize()
+    assert torch.equal(out_a.view(torch.int32), out_b.view(torch.int32))
+    # a larger frame grows the bound workspace
+    assert lib.snx_model_bind(h, 2 * W, 2 * H, None, C.byref(view)) == 0
+    assert view.workspace_bytes >= snx.snx_cnn_workspace_size(2 * W, 2 * H, 1, 0)
+    assert lib.snx_model_destroy(h) == 0

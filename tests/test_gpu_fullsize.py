@@ -2,9 +2,10 @@
 planes+quadrics frame, at sampled pixels whose reference the oracle computes on
 a crop holding everything the pixel depends on:
 
-* star-fill support (8 directions, 10 steps, CD k = 0.05 and ST t = 2): a
-  pixel's rays reach 10 px and the depth Laplacian one more, so a crop of
-  radius 11 (cut at the image border) gives its exact support;
+* star-fill support (8 directions x 10 steps and 16 directions x 30 steps,
+  covered depth and ST t = 2): a pixel's rays reach `steps` px and the depth
+  Laplacian one more, so a crop of radius steps + 1 (cut at the image border)
+  gives its exact support;
 * component-restricted 9x9 window: radius 4, with the frame's labels.
 
 Definedness must agree exactly; A within the square-window tolerance."""
@@ -59,22 +60,26 @@ def frame():
     return sc, d, dn, lab
 
 
-@pytest.mark.parametrize("stop,thr", [(0, 0.05), (1, 2.0)])
-def test_star_full_frame_sampled(oracle, frame, stop, thr):
+@pytest.mark.parametrize("dirs,steps,stop,thr", [(8, 10, 0, 0.05), (8, 10, 1, 2.0),
+                                                  (16, 30, 0, 0.1), (16, 30, 1, 2.0)])
+def test_star_full_frame_sampled(oracle, frame, dirs, steps, stop, thr):
+    """Also the paper's own adaptive configurations, 16 directions x 30 steps
+    (Sec. 4, the 1024x720 timing table): crop radius steps + 1."""
     snx = _snx()
     sc, _, dn, _ = frame
-    print(f"case star full frame stop {stop} thr {thr}", flush=True)
+    print(f"case star full frame {dirs} dirs {steps} steps stop {stop} thr {thr}", flush=True)
     cam = _cam32(sc.cam)
     H, W = dn.shape
     aff = torch.empty((2, H, W), device=DEV)
-    snx.snx_affine_normals_star(dn, cam, affine=aff, directions=8, steps=10, stop=stop,
+    snx.snx_affine_normals_star(dn, cam, affine=aff, directions=dirs, steps=steps, stop=stop,
                                 threshold=thr)
     torch.cuda.synchronize()
     a = aff.cpu().numpy()
     D = dn.cpu().numpy().astype(np.float64)
+    rr = steps + 1
     for v, u in _samples(H, W):
-        v0, v1, u0, u1 = max(0, v - 11), min(H, v + 12), max(0, u - 11), min(W, u + 12)
-        r1, r2, rd = oracle.star_affine(D[v0:v1, u0:u1], 8, 10, stop, thr, cam=cam)
+        v0, v1, u0, u1 = max(0, v - rr), min(H, v + rr + 1), max(0, u - rr), min(W, u + rr + 1)
+        r1, r2, rd = oracle.star_affine(D[v0:v1, u0:u1], dirs, steps, stop, thr, cam=cam)
         _cmp(a, (r1[v - v0, u - u0], r2[v - v0, u - u0]), rd[v - v0, u - u0], v, u)
 
 

@@ -83,6 +83,13 @@ CASES = [
     (1, 1, 8, 5, "cd", 0.05, 0, 0),
     (5, 3, 4, 2, "st", 0.8, 0, 0),
     (64, 16, 8, 32, "st", 0.9, 0, 0),
+    (160, 120, 16, 10, "cd", 0.05, 0, 0),
+    (130, 70, 16, 10, "st", 0.8, 0, 2),
+    (200, 150, 16, 30, "cd", 0.1, 0, 0),
+    (67, 19, 16, 1, "cd", 0.5, 8, 0),        # one step: at most 8 distinct pixels
+    (90, 40, 16, 12, "cd", 0.2, 60, 0),
+    (5, 3, 16, 2, "st", 0.8, 0, 0),
+    (64, 16, 16, 32, "st", 0.9, 0, 0),
 ]
 
 

@@ -134,3 +134,41 @@ def test_fidelity_term_closed_form_and_gradient():
         Dm = Dt.copy(); Dm.flat[j] -= 1e-6
         fd = (cnn.fidelity_loss(Dp, clean)[0] - cnn.fidelity_loss(Dm, clean)[0]) / 2e-6
         assert abs(fd - g.flat[j]) < 1e-8
+
+
+def test_backward_rounding_replay():
+    """Scale of the GPU's backward rounding (bfloat16 gradients, FP32 sums)
+    against the FP64 oracle backward, on the GPU gradient test's inputs: the
+    roundings alone move each layer's gradient by under 1 %, visibly so on every
+    layer before the last; FP32 summation order in the forward (bfloat16 flips
+    of single activations) and the backward adds at most 1.5 % on top.  The GPU
+    test's per-layer bound is 3x the sum of the two, computed on its inputs."""
+    from tests import cnn_replay
+    rng = np.random.default_rng(2)
+    p = cnn.init_params(2)
+    p = [(w + rng.normal(0, 0.05, w.shape) * (k == 5), b + rng.normal(0, 0.02, b.shape))
+         for k, (w, b) in enumerate(p)]
+    p32 = [(w.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64))
+           for w, b in p]
+    nrm = np.linalg.norm
+    sizes = [lw.size + lb.size for lw, lb in p32]
+    for i in range(2):
+        c = scenes.training_crop(i, crop=48)
+        Dt = cnn.forward(c.disp, p32, True)
+        _, _, _, dDt = cnn.normal_loss(Dt, c.normal, c.cam, 5)
+        ora = cnn_replay.flat(cnn.backward(c.disp, p32, dDt, True))
+        r64 = cnn_replay.flat(cnn_replay.replay(c.disp, p32, dDt))
+        r32 = [cnn_replay.flat(cnn_replay.replay(c.disp, p32, dDt,
+                                                 order=np.random.default_rng(s)))
+               for s in range(3)]
+        off = 0
+        for k, n in enumerate(sizes):
+            o, q = ora[off:off + n], r64[off:off + n]
+            rel = nrm(q - o) / nrm(o)
+            assert rel < 1e-2, (i, k, rel)
+            if k < 5:
+                assert rel > 1e-5, (i, k, rel)      # the roundings are visible
+            for r in r32:
+                spread = nrm(r[off:off + n] - q) / nrm(q)
+                assert spread <= 1.5e-2, (i, k, spread)
+            off += n

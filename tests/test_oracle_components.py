@@ -7,23 +7,39 @@ import pytest
 from synth import scenes
 
 
-def _closure_labels(D, k_rel, t_abs):
-    """Min-index labels from the transitive closure of the 4-neighbour edge
-    relation, with the predicate evaluated in exact rational arithmetic."""
+def _exact_edges(D, k_rel, t_abs):
+    """Per-pixel edge bits of the covered-depth predicate in exact rational
+    arithmetic: bit 0 valid, bit 1 joined to the left, bit 2 joined above."""
     H, W = D.shape
-    N = H * W
     valid = np.isfinite(D) & (D > 0)
-    adj = np.eye(N, dtype=bool) & valid.reshape(-1)[:, None]
+    flags = valid.astype(np.uint8)
     kq, tq = Fraction(float(np.float32(k_rel))), Fraction(float(np.float32(t_abs)))
     for v in range(H):
         for u in range(W):
-            for du, dv in ((1, 0), (0, 1)):
+            for du, dv, bit in ((1, 0, 2), (0, 1, 4)):
                 uu, vv = u + du, v + dv
                 if uu >= W or vv >= H or not (valid[v, u] and valid[vv, uu]):
                     continue
                 a, b = Fraction(float(D[v, u])), Fraction(float(D[vv, uu]))
                 if abs(a - b) <= max(tq, kq * min(a, b)):
-                    p, q = v * W + u, vv * W + uu
+                    flags[vv, uu] |= bit
+    return flags
+
+
+def _closure_from_flags(flags):
+    """Min-index labels from the transitive closure of the 4-neighbour graph
+    given by edge bits (bit 0 present, bit 1 edge left, bit 2 edge up; an edge
+    counts between two present pixels)."""
+    H, W = flags.shape
+    N = H * W
+    present = (flags & 1).astype(bool).reshape(-1)
+    adj = np.eye(N, dtype=bool) & present[:, None]
+    for v in range(H):
+        for u in range(W):
+            q = v * W + u
+            for bit, p in ((2, q - 1), (4, q - W)):
+                if flags[v, u] & bit and (bit == 2 and u > 0 or bit == 4 and v > 0) \
+                        and present[p] and present[q]:
                     adj[p, q] = adj[q, p] = True
     reach = adj.copy()
     while True:
@@ -33,9 +49,15 @@ def _closure_labels(D, k_rel, t_abs):
         reach = nxt
     lab = np.full(N, -1, np.int32)
     for p in range(N):
-        if valid.reshape(-1)[p]:
+        if present[p]:
             lab[p] = np.flatnonzero(reach[p])[0]
     return lab.reshape(H, W), int(len(set(lab[lab >= 0].tolist())))
+
+
+def _closure_labels(D, k_rel, t_abs):
+    """Min-index labels from the transitive closure of the 4-neighbour edge
+    relation, with the predicate evaluated in exact rational arithmetic."""
+    return _closure_from_flags(_exact_edges(D, k_rel, t_abs))
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -109,3 +131,36 @@ def test_all_invalid_and_empty_rows(oracle):
     D = np.full((1, 7), 3.0, np.float32)
     lab, n = oracle.components(D)
     assert n == 1 and np.all(lab == 0)
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("shape", [None, (9, 1), (1, 9), (2, 2)])
+def test_edge_graph_bfs_against_transitive_closure(oracle, seed, shape):
+    """The oracle's labelling of an explicitly given edge graph (the exhaustive
+    GPU test's reference) against the transitive closure of the same graph:
+    random presence and edge bits, including bits on absent pixels and on the
+    image border (which must be ignored); single-column and single-row frames,
+    where the index step to the neighbour below equals the step to the right."""
+    rng = np.random.default_rng(100 + seed)
+    H, W = rng.integers(1, 9, 2) if shape is None else shape
+    flags = (rng.random((H, W)) < 0.8).astype(np.uint8)
+    flags |= (rng.random((H, W)) < 0.6).astype(np.uint8) << 1
+    flags |= (rng.random((H, W)) < 0.6).astype(np.uint8) << 2
+    lab, n = oracle.components_edges(flags)
+    ref, nref = _closure_from_flags(flags)
+    np.testing.assert_array_equal(lab, ref)
+    assert n == nref
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_edge_graph_of_the_predicate_equals_components(oracle, seed):
+    """Posing the covered-depth predicate's own edges as an explicit graph gives
+    the disparity labelling back."""
+    rng = np.random.default_rng(200 + seed)
+    D = rng.choice([5.0, 5.4, 6.0, 9.0, 9.9, 20.0], size=(12, 17)) + rng.normal(0, 0.05, (12, 17))
+    D = D.astype(np.float32)
+    D[rng.random(D.shape) < 0.1] = np.nan
+    lab, n = oracle.components(D, 0.1, 0.5)
+    lab_e, n_e = oracle.components_edges(_exact_edges(D, 0.1, 0.5))
+    np.testing.assert_array_equal(lab, lab_e)
+    assert n == n_e

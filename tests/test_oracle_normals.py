@@ -81,20 +81,29 @@ def test_printed_sign_of_b_would_fail(oracle):
 
 
 def test_sphere_table_soft_pin(oracle):
-    """The paper's sphere table (Sec. 4): plain n x n affine estimator, no
-    pre-filter.  Tolerance: max(0.12 deg, 0.5 %) -- Monte-Carlo spread of one
-    noise draw plus the focal length the paper does not state (500 px assumed)."""
+    """The paper's sphere table (Sec. 4, Table noise-compare, Affine rows):
+    plain n x n affine estimator, no pre-filter, mean over 8 noise draws.
+    Tolerance 0.15 deg for n <= 9 and 0.2 deg for n = 15.  The paper's figure is
+    one noise draw: over seeds the mean of one draw spreads by 0.01-0.08 deg
+    (standard deviation), so a single draw lies within about 0.15 deg of the
+    expectation; the focal length (not stated, 500 px assumed) and the handling
+    of the sphere's rim add a small systematic part (at n = 15, sigma = 0.2 the
+    paper's 0.97 deg against 0.89 deg here)."""
     tab = json.load(open(os.path.join(GOLDEN, "sphere_noise_table.json")))
     for key, sigma in (("sigma_0.2", 0.2), ("sigma_1.0", 1.0)):
-        sc = scenes.sphere_scene(sigma=sigma, seed=0)
-        D = sc.disp.astype(np.float64)
+        ours = {n: [] for n in tab["window"]}
+        for seed in range(8):
+            sc = scenes.sphere_scene(sigma=sigma, seed=seed)
+            D = sc.disp.astype(np.float64)
+            for n in tab["window"]:
+                a1, a2, d = oracle.affine(D, n)
+                nrm = oracle.normals(D, a1, a2, d, sc.cam)
+                m = d & np.isfinite(sc.normal[..., 0])
+                ours[n].append(angle_deg(nrm, sc.normal)[m].mean())
         for n, paper in zip(tab["window"], tab[key]):
-            a1, a2, d = oracle.affine(D, n)
-            nrm = oracle.normals(D, a1, a2, d, sc.cam)
-            m = d & np.isfinite(sc.normal[..., 0])
-            ours = angle_deg(nrm, sc.normal)[m].mean()
-            tol = max(0.12, 0.005 * paper)
-            assert abs(ours - paper) <= tol, (sigma, n, ours, paper)
+            tol = 0.15 if n <= 9 else 0.2
+            mean = float(np.mean(ours[n]))
+            assert abs(mean - paper) <= tol, (sigma, n, mean, paper)
 
 
 def test_point_cloud_reprojects(oracle):

@@ -7,7 +7,10 @@ Estimation) against facts fixed independently of its code:
   window mixes the two);
 * supports of hand-built cases, worked out by hand from the stopping rules
   (an invalid pixel, a covered-depth crossing, a depth-Laplacian spike);
-* the exact step at which the covered-depth rule stops a ray on a ramp.
+* the exact step at which the covered-depth rule stops a ray on a ramp;
+* 16 directions: the support drawn by hand from the ray reading (directions
+  2 pi m / 16 scaled to a unit larger component, offsets rounded to the
+  nearest pixel; neighbouring rays share their first pixel, which counts once).
 """
 import numpy as np
 import pytest
@@ -27,7 +30,7 @@ def _plane(W, H, d0, gu, gv):
     return d0 + gu * u + gv * v
 
 
-@pytest.mark.parametrize("dirs", [4, 8])
+@pytest.mark.parametrize("dirs", [4, 8, 16])
 @pytest.mark.parametrize("steps,stop,thr", [(3, CD, 0.5), (7, CD, 0.01), (5, ST, 1e9), (6, CD, 0.02)])
 def test_plane_slope_exact_on_any_support(dirs, steps, stop, thr):
     gu, gv = 0.125, -0.0625                     # exact binary fractions
@@ -132,3 +135,55 @@ def test_cd_is_a_depth_range_not_a_disparity_range():
         D[2, 3] = d1
         m = oracle.star_mask(D, 2, 2, 4, 1, CD, 0.5)
         assert m[1, 1 + 1] == taken, d1
+
+
+# The 16-direction star of 3 steps on a full window, drawn by hand: the 8
+# compass rays (axes, diagonals) take 3 pixels each; the 8 rays in between
+# (tan 22.5 deg = 0.414: offsets (1, 0), (2, 1), (3, 1) for the first one, the
+# rest by symmetry) share their first pixel with an axis ray, so they add 2
+# each: 24 + 16 = 40 pixels.  Rows are v = -3 .. 3, columns u = -3 .. 3.
+STAR16_3 = ["#.###.#",
+            ".#####.",
+            "#######",
+            "###.###",
+            "#######",
+            ".#####.",
+            "#.###.#"]
+
+
+def test_star16_mask_by_hand():
+    # the hand drawing above, derived ray by ray
+    want = np.zeros((7, 7), np.uint8)
+    dirs8 = [(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1)]
+    for dx, dy in dirs8:
+        for k in (1, 2, 3):
+            want[3 + k * dy, 3 + k * dx] = 1
+    # the in-between rays: major component k, minor round(0.414 k) = 0, 1, 1
+    for sx in (-1, 1):
+        for sy in (-1, 1):
+            for k, r in ((2, 1), (3, 1)):
+                want[3 + sy * r, 3 + sx * k] = 1          # near the u axis
+                want[3 + sy * k, 3 + sx * r] = 1          # near the v axis
+    drawn = np.array([[c == "#" for c in row] for row in STAR16_3], np.uint8)
+    np.testing.assert_array_equal(want, drawn)
+    assert int(want.sum()) == 40
+    D = _plane(21, 21, 30.0, 0.0, 0.0)
+    mask = oracle.star_mask(D, 10, 10, dirs=16, steps=3, stop=CD, thr=0.5)
+    np.testing.assert_array_equal(mask, want.astype(bool))
+    # 8 directions are the compass subset of the same reading
+    m8 = oracle.star_mask(D, 10, 10, dirs=8, steps=3, stop=CD, thr=0.5)
+    assert m8.sum() == 24 and not np.any(m8 & ~want.astype(bool))
+
+
+def test_star16_shared_first_pixel():
+    """An invalid pixel right of the centre stops the u+ axis ray and both
+    in-between rays next to it at their first step (they would share it)."""
+    D = _plane(21, 21, 30.0, 0.0, 0.0)
+    D[10, 11] = np.nan
+    mask = oracle.star_mask(D, 10, 10, dirs=16, steps=3, stop=CD, thr=0.5)
+    want = np.array([[c == "#" for c in row] for row in STAR16_3], bool)
+    want[3, 4:] = False               # the u+ axis ray: (1,0), (2,0), (3,0)
+    want[2, 5:] = False               # the ray at -22.5 deg: (2,-1), (3,-1)
+    want[4, 5:] = False               # the ray at +22.5 deg: (2,1), (3,1)
+    np.testing.assert_array_equal(mask, want)
+    assert mask.sum() == 40 - 3 - 2 - 2
