@@ -287,6 +287,20 @@ snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t he
                               snx_point *out, int32_t *count,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* snx_compact_points_noalloc -- snx_compact_points for callers that cannot
+ * allocate or pass device memory of their own (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * output as snx_compact_points without the workspace: the chunk counts and
+ * offsets live in a static 64 KiB device array of the library (one copy per
+ * GPU, held until the process ends; its address is looked up once per device on
+ * the first call there).  The call allocates nothing.  Limit: width * height <=
+ * 33 554 432 records (8192 chunks of 4096); larger frames return
+ * SNX_ERR_UNSUPPORTED before anything is launched.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (concurrent streams,
+ * host threads) race and must be serialised by the caller. */
+snx_status snx_compact_points_noalloc(const snx_point *points, int32_t width, int32_t height,
+                                      snx_point *out, int32_t *count, void *stream);
+
 /* ---------------------------------------------------------------------------
  * snx_oriented_point_cloud -- filter, gradients, A, normal and point records in
  * ONE kernel, given component labels already computed by snx_components on the

@@ -118,6 +118,7 @@ SIGNATURES = {
                                   _P, _P, _P, _I32, C.c_float, C.c_float, C.c_float, C.c_float,
                                   _P, _P, _SZ, _P]),
     "snx_components_from_edges": (_I32, [_P, _I64, _I32, _I32, _P, _I64, _P, _P, _SZ, _P]),
+    "snx_compact_points_noalloc": (_I32, [_P, _I32, _I32, _P, _P, _P]),
     "snx_model_create": (_I32, [_P, _P, _P, C.POINTER(snx_model_info), C.POINTER(C.c_void_p)]),
     "snx_model_load": (_I32, [C.c_char_p, C.POINTER(C.c_void_p)]),
     "snx_model_save": (_I32, [_P, C.c_char_p]),
@@ -284,6 +285,27 @@ def snx_compact_points(points, out, count, workspace, stream=None):
     _check(load().snx_compact_points(_ptr(points), W, H, _ptr(out), _ptr(count), _ptr(workspace),
                                      workspace.numel() * workspace.element_size(),
                                      _stream(stream)))
+
+
+def snx_compact_points_noalloc(points, out, count, stream=None):
+    """snx_compact_points without a workspace: the library's own static device
+    scratch (allocates nothing; frames up to 33 554 432 records; calls that
+    overlap on one GPU race)."""
+    import torch
+    if points.dim() != 3 or points.shape[2] != 8 or points.dtype != torch.float32:
+        raise ValueError("points must be [H, W, 8] float32 records")
+    if not points.is_contiguous() or not out.is_contiguous():
+        raise ValueError("points and out must be contiguous")
+    H, W = points.shape[0], points.shape[1]
+    if out.dtype != torch.float32 or out.numel() < H * W * 8:
+        raise ValueError("out must be float32 with room for H*W records")
+    if count.dtype != torch.int32 or count.numel() < 1:
+        raise ValueError("count must be an int32 tensor")
+    for t in (points, out, count):
+        if t.device.type != "cuda":
+            raise ValueError("tensors must be on the GPU")
+    _check(load().snx_compact_points_noalloc(_ptr(points), W, H, _ptr(out), _ptr(count),
+                                             _stream(stream)))
 
 
 def snx_affine_normals_labels(disp_dn, labels, cam, affine=None, normals=None, window=9,

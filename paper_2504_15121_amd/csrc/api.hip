@@ -241,6 +241,32 @@ snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t he
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points");
 }
 
+snx_status snx_compact_points_noalloc(const snx_point *points, int32_t width, int32_t height,
+                                      snx_point *out, int32_t *count, void *stream)
+{
+    g_err[0] = 0;
+    if (!size_ok(width, height)) return fail(SNX_ERR_ARG, "bad size %d x %d", width, height);
+    if (!count) return fail(SNX_ERR_ARG, "count is NULL");
+    const int64_t n = (int64_t)width * height;
+    if (n > snx::compact_noalloc_max_records())
+        return fail(SNX_ERR_UNSUPPORTED, "%lld records exceed the allocation-free limit of %lld",
+                    (long long)n, (long long)snx::compact_noalloc_max_records());
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        hipError_t e = snx::launch_fill_i32(count, 0, 1, s);
+        return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points_noalloc");
+    }
+    if (!points || !out) return fail(SNX_ERR_ARG, "points or out is NULL");
+    const char *pb = reinterpret_cast<const char *>(points), *ob = reinterpret_cast<const char *>(out);
+    const int64_t bytes = n * (int64_t)sizeof(snx_point);
+    if (pb < ob + bytes && ob < pb + bytes) return fail(SNX_ERR_ARG, "out overlaps points");
+    int32_t *cc = nullptr, *co = nullptr;
+    hipError_t e = snx::compact_noalloc_scratch(&cc, &co);
+    if (e != hipSuccess) return hip_fail(e, "snx_compact_points_noalloc (scratch address)");
+    e = snx::launch_compact(points, n, out, count, cc, co, s);
+    return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points_noalloc");
+}
+
 snx_status snx_affine_normals_labels(const float *disp_dn, int64_t stride, const int32_t *labels,
                                      int64_t label_stride, int32_t width, int32_t height,
                                      const snx_camera *cam, const snx_normal_params *params,

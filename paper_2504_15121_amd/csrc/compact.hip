@@ -6,7 +6,18 @@
 // counts into exclusive offsets (and the total); (3) each workgroup writes its
 // chunk's defined records from its offset, ranks within a wave from a ballot,
 // wave offsets through LDS, so the output order is the input order.
+#include <atomic>
+#include <mutex>
+
 #include "snx_internal.hpp"
+
+// Scratch of the allocation-free compaction (snx_compact_points_noalloc): the
+// chunk counts in the first half, the chunk offsets in the second.  Every kernel
+// writes each entry it later reads, so nothing needs clearing between calls.
+// Host code must not pass this name to a kernel (on the host it is only a
+// stand-in): the per-device address comes from hipGetSymbolAddress below.
+constexpr int64_t kNoAllocChunks = 8192;
+static __device__ __align__(256) int32_t scratch[2 * kNoAllocChunks];
 
 namespace snx {
 namespace {
@@ -100,6 +111,39 @@ k_compact_scatter(const snx_point *in, int64_t n, const int32_t *chunk_off, snx_
 }  // namespace
 
 int64_t compact_chunks(int64_t n) { return (n + kCpChunk - 1) / kCpChunk; }
+
+int64_t compact_noalloc_max_records() { return kNoAllocChunks * kCpChunk; }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<int32_t *> g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t compact_noalloc_scratch(int32_t **chunk_count, int32_t **chunk_off)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    int32_t *p = g_scratch[dev].load(std::memory_order_acquire);
+    if (!p) {
+        // first call on this device (which is current): look up this device's
+        // copy of the array once and keep its address
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch[dev].load(std::memory_order_relaxed);
+        if (!p) {
+            void *addr = nullptr;
+            if ((e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+            if (!addr) return hipErrorInvalidSymbol;
+            p = static_cast<int32_t *>(addr);
+            g_scratch[dev].store(p, std::memory_order_release);
+        }
+    }
+    *chunk_count = p;
+    *chunk_off = p + kNoAllocChunks;
+    return hipSuccess;
+}
 
 hipError_t launch_compact(const snx_point *in, int64_t n, snx_point *out, int32_t *count,
                           int32_t *chunk_count, int32_t *chunk_off, hipStream_t s)

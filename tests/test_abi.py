@@ -24,7 +24,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 35
+    assert len(names) == 36
     for n in names:
         assert hasattr(lib, n), n
     from paper_2504_15121_amd import _lib
@@ -252,6 +252,18 @@ def test_plan_validation(lib):
     assert lib.snx_plan_create(C.cast(bad, C.c_void_p), 1, C.byref(_dn()), C.byref(nr),
                                C.byref(cp), C.byref(out)) == 1                  # stride < width
     assert lib.snx_plan_run(None, None) == 1
+
+
+def test_compact_noalloc_validation(lib):
+    """The allocation-free compaction refuses frames over its static scratch
+    (33 554 432 records) and bad arguments before any HIP call."""
+    assert lib.snx_compact_points_noalloc(FAKE, 8192, 4097, C.c_void_p(0x900000000), FAKE,
+                                          None) == 2
+    assert b"allocation-free limit" in lib.snx_last_error()
+    assert lib.snx_compact_points_noalloc(FAKE, 64, 8, FAKE, None, None) == 1     # no count
+    assert lib.snx_compact_points_noalloc(None, 64, 8, FAKE, FAKE, None) == 1     # no points
+    assert lib.snx_compact_points_noalloc(FAKE, -1, 8, FAKE, FAKE, None) == 1
+    assert lib.snx_compact_points_noalloc(FAKE, 64, 8, FAKE, FAKE, None) == 1     # overlap
 
 
 # ---------------------------------------------------------------- model files
