@@ -490,6 +490,18 @@ def bench_small_frame(snx, torch, dev, nf, ng, replays=1000):
     plan = snx.Plan([f], filter_window=nf, normal_window=ng)
     stream = torch.cuda.Stream()
     ms = _time_replays(snx, torch, plan, stream, replays, warmup=3)
+    # the same plan launched directly (no graph) on torch's stream
+    for _ in range(3):
+        plan.run(0)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(replays):
+        plan.run(0)
+    b.record()
+    torch.cuda.synchronize()
+    ms_direct = a.elapsed_time(b) / replays
     plan.close()
     ws = torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8, device=dev)
     call = lambda: snx.snx_pipeline(f["disp"], sc.cam, f["labels"], f["points"], ws,
@@ -509,6 +521,7 @@ def bench_small_frame(snx, torch, dev, nf, ng, replays=1000):
     return {"workload": "planes_640x480", "width": W, "height": H,
             "graph_replays": replays, "us_per_frame_graph": round(ms * 1e3, 2),
             "value_graph": round(W * H / (ms * 1e-3) / 1e6, 1),
+            "us_per_frame_plan_direct": round(ms_direct * 1e3, 2),
             "us_per_frame_calls": round(ms_call * 1e3, 2),
             "value_calls": round(W * H / (ms_call * 1e-3) / 1e6, 1), "unit": "Mpixel/s",
             "filter": f"lsq{nf}", "normal_window": ng}

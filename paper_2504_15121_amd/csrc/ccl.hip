@@ -347,9 +347,6 @@ __device__ __forceinline__ void merge_pair(const E &edge_at, bool shortcut, int 
         q = p + W;
         vert = false;
     }
-    // the forest entries are fetched together with the disparities, so that an
-    // edge costs one round trip before the hook
-    int a = gload(par + p), b = gload(par + q);
     if (!edge_at(yp, xp, yq, xq)) return;
     if (shortcut) {
         if (vert ? yp % kCH != 0 && edge_at(yp - 1, xp, yp - 1, xq) &&
@@ -363,6 +360,7 @@ __device__ __forceinline__ void merge_pair(const E &edge_at, bool shortcut, int 
     // the smaller at once.  If it was still a root the union is done in two
     // round trips; otherwise its old parent, like it an ancestor of one side,
     // is united with the other side by the general path.
+    int a = gload(par + p), b = gload(par + q);
     if (a == b) return;
     if (a < b) { const int t = a; a = b; b = t; }
     const int old = atomicMin(par + a, b);

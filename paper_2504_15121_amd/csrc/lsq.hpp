@@ -244,43 +244,72 @@ __device__ __forceinline__ bool slope_solve(const ColMom &m, float Dc, int need_
     return true;
 }
 
-// 3x3 mask moments packed in 5-bit fields: N | Sx+8 | Sy+8 | Sxx | Sxy+8 | Syy.
-constexpr int tap3(int dx, int dy)
-{
-    return 1 + dx * (1 << 5) + dy * (1 << 10) + dx * dx * (1 << 15) + dx * dy * (1 << 20) +
-           dy * dy * (1 << 25);
-}
-constexpr int kTap3Init = 8 * (1 << 5) + 8 * (1 << 10) + 8 * (1 << 20);
+// 3x3 filter by mask.  For the valid taps of a 3x3 window (9-bit mask, bit
+// 3 (dy + 1) + dx + 1), the intercept of the LSQ plane is a fixed linear
+// combination of the data moments: with the integer normal matrix
+// M = sum (1, dx, dy)^T (1, dx, dy) and r = (R0, Rx, Ry),
+//   h = (M^-1 r)_0 = (m11 R0 - m12 Rx + m13 Ry) / det M
+// (m11 = Sxx Syy - Sxy^2, m12 = Sx Syy - Sxy Sy, m13 = Sx Sxy - Sxx Sy; the
+// centred form D_c + (M^-1 (r - D_c M e_0))_0 is the same number).  The three
+// weights of every mask are tabulated once; a singular M is marked by a NaN
+// weight (pass-through).
+struct Filter3Table {
+    double w[512][4];
+    constexpr Filter3Table() : w()
+    {
+        for (int m = 0; m < 512; ++m) {
+            long long n = 0, sx = 0, sy = 0, sxx = 0, sxy = 0, syy = 0;
+            for (int k = 0; k < 9; ++k) {
+                if (!((m >> k) & 1)) continue;
+                const long long dx = k % 3 - 1, dy = k / 3 - 1;
+                n += 1;
+                sx += dx;
+                sy += dy;
+                sxx += dx * dx;
+                sxy += dx * dy;
+                syy += dy * dy;
+            }
+            const long long m11 = sxx * syy - sxy * sxy;
+            const long long m12 = sx * syy - sxy * sy;
+            const long long m13 = sx * sxy - sxx * sy;
+            const long long det = n * m11 - sx * m12 + sy * m13;
+            if (det == 0) {
+                w[m][0] = __builtin_nan("");
+                w[m][1] = w[m][2] = w[m][3] = 0.0;
+            } else {
+                w[m][0] = (double)m11 / (double)det;
+                w[m][1] = -(double)m12 / (double)det;
+                w[m][2] = (double)m13 / (double)det;
+                w[m][3] = 0.0;
+            }
+        }
+    }
+};
+static __constant__ const Filter3Table kFilter3 = Filter3Table();
 
 // Direct 3x3 filter around the validity-coded value p[0] (row stride ld), for
-// a valid centre.  Every kernel that filters with n_f = 3 calls this.
+// a valid centre: pass-through when fewer than need_f taps are valid or the
+// normal matrix is singular.  Every kernel that filters with n_f = 3 calls this.
 __device__ __forceinline__ float filter3x3(const float *p, int ld, int need_f)
 {
-    int c = kTap3Init;
+    int msk = 0;
     double R0 = 0.0, Rx = 0.0, Ry = 0.0;
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy) {
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
             const float v = p[dy * ld + dx];
-            c += v > 0.0f ? tap3(dx, dy) : 0;
+            msk |= (v > 0.0f ? 1 : 0) << (3 * (dy + 1) + dx + 1);
             const double dv = (double)v;
             R0 += dv;
             if (dx != 0) Rx += (double)dx * dv;
             if (dy != 0) Ry += (double)dy * dv;
         }
     }
-    ColMom m;
-    m.N = c & 31;
-    m.Sx = ((c >> 5) & 31) - 8;
-    m.Sy = ((c >> 10) & 31) - 8;
-    m.Sxx = (c >> 15) & 31;
-    m.Sxy = ((c >> 20) & 31) - 8;
-    m.Syy = (c >> 25) & 31;
-    m.R0 = R0;
-    m.Rx = Rx;
-    m.Ry = Ry;
-    return filter_solve(m, p[0], need_f);
+    const double *w = kFilter3.w[msk];
+    const double w0 = w[0];
+    if (__popc(msk) < need_f || w0 != w0) return p[0];
+    return (float)(w0 * R0 + w[1] * Rx + w[2] * Ry);
 }
 
 // Unit normal n = -m/|m| with m = (f_x g_u, f_y g_v, D - (u-u0) g_u - (v-v0) g_v).

@@ -19,6 +19,8 @@
 namespace snx {
 namespace {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 struct Layout {
     int R, inW, inH, dtW, dtH;
     size_t off_dt, off_ab, off_s, bytes;
@@ -104,37 +106,51 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
         constexpr int sR = (RF > 0 ? RF : 0) + (RG > 0 ? RG : 0);
         constexpr int sW = kTileW + 2 * sR, sH = (TH > 0 ? TH : 1) + 2 * sR;
         constexpr int NT = sW * sH, NL = (NT + NB - 1) / NB;
+        // a tile whose rows (with halo) lie inside the frame and start on a
+        // 16-byte boundary reads them as aligned 16-byte loads
+        constexpr int Q = sW / 4, NQ = Q * sH, NLQ = (NQ + NB - 1) / NB;
+        const bool vec = sR % 4 == 0 && x0 - sR >= 0 && x0 + kTileW + sR <= a.W &&
+                         (a.ld_src & 3) == 0 && ((uintptr_t)a.src & 15) == 0;
         float v[NL];
+        f32x4 q[NLQ];
+        if (vec) {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int e = tid + k * NB;
-            const int ly = e / sW, lx = e - ly * sW;
-            const int gy = y0 - sR + ly, gx = x0 - sR + lx;
-            v[k] = 0.0f;
-            if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                v[k] = __builtin_nontemporal_load(a.src + (int64_t)gy * a.ld_src + gx);
-        }
-        // while the tile loads are in flight, resolve every owned pixel's
-        // forest entry to its root, all chains advancing together
-        if (rg > 0 && a.forest) {
-            bool again = true;
-            while (again) {
-                again = false;
-                int32_t nx[RPT * kPairs];
+            for (int k = 0; k < NLQ; ++k) {
+                const int e = tid + k * NB;
+                const int ly = e / Q, c = e - ly * Q;
+                const int gy = y0 - sR + ly;
+                q[k] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+                if (e < NQ && gy >= 0 && gy < a.H)
+                    q[k] = __builtin_nontemporal_load(
+                        reinterpret_cast<const f32x4 *>(a.src + (int64_t)gy * a.ld_src + x0 - sR) + c);
+            }
+        } else {
 #pragma unroll
-                for (int k = 0; k < RPT * kPairs; ++k) nx[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
-#pragma unroll
-                for (int k = 0; k < RPT * kPairs; ++k)
-                    if (nx[k] != labr[k]) {
-                        labr[k] = nx[k];
-                        again = true;
-                    }
+            for (int k = 0; k < NL; ++k) {
+                const int e = tid + k * NB;
+                const int ly = e / sW, lx = e - ly * sW;
+                const int gy = y0 - sR + ly, gx = x0 - sR + lx;
+                v[k] = 0.0f;
+                if (e < NT && gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                    v[k] = __builtin_nontemporal_load(a.src + (int64_t)gy * a.ld_src + gx);
             }
         }
+        if (vec) {
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int e = tid + k * NB;
-            if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
+            for (int k = 0; k < NLQ; ++k) {
+                const int e = tid + k * NB;
+                if (e < NQ) {
+                    float *d = sIn + 4 * e;     // row-major with sW = 4 Q floats a row
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) d[i] = valid_disp(q[k][i]) ? q[k][i] : 0.0f;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const int e = tid + k * NB;
+                if (e < NT) sIn[e] = valid_disp(v[k]) ? v[k] : 0.0f;
+            }
         }
     } else {
         for (int e = tid; e < L.inH * L.inW; e += NB) {
@@ -203,12 +219,42 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     // at every step of the runs the lanes of a wave write consecutive slots (no
     // LDS bank conflicts), and a row's 64 columns still fill its 64 slots.
     constexpr int kRun = 4, kRuns = kTileW / kRun;
+    // The owned pixels' forest entries are resolved to their roots around the
+    // row pass: the first step's loads are issued before it and consumed after
+    // it (global loads and LDS work wait on separate counters), the rest of the
+    // chains advance together afterwards.
+    constexpr bool kChase = RF >= 0 && RG >= 0 && TH > 0;
+    int32_t hop[kChase ? RPT * kPairs : 1];
+    if (kChase && a.forest) {
+#pragma unroll
+        for (int k = 0; k < RPT * kPairs; ++k) hop[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
+    }
     for (int e = tid; e < L.dtH * kRuns; e += NB) {
         const int ly = e / kRuns, run = e - ly * kRuns;
         row_moments_run<RG, kRun, kRuns>(sDt + ly * L.dtW + run * kRun, rg,
                                          sAB + ly * kTileW + run, sS + ly * kTileW + run);
     }
     __syncthreads();
+    if (kChase && a.forest) {
+        bool again = false;
+#pragma unroll
+        for (int k = 0; k < RPT * kPairs; ++k)
+            if (hop[k] != labr[k]) {
+                labr[k] = hop[k];
+                again = true;
+            }
+        while (again) {
+            again = false;
+#pragma unroll
+            for (int k = 0; k < RPT * kPairs; ++k) hop[k] = labr[k] >= 0 ? a.forest[labr[k]] : labr[k];
+#pragma unroll
+            for (int k = 0; k < RPT * kPairs; ++k)
+                if (hop[k] != labr[k]) {
+                    labr[k] = hop[k];
+                    again = true;
+                }
+        }
+    }
     // column moments: the first row of a run by direct sums, the others by
     // sliding the window down one row.  The runs are unrolled for the static
     // tile heights so that the per-run label registers are indexed statically.
@@ -293,8 +339,9 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
     }
 }
 
+// two 512-thread workgroups per CU need at most 128 VGPRs (4 waves a SIMD)
 template <int RF, int RG, int TH>
-__global__ void __launch_bounds__(stencil_block(TH))
+__global__ void __launch_bounds__(stencil_block(TH)) __attribute__((amdgpu_waves_per_eu(4)))
 k_stencil(StencilArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -306,7 +353,7 @@ k_stencil(StencilArgs a)
 
 // Persistent back stage over the (frame, tile) work list of a batch.
 template <int RG, int TH>
-__global__ void __launch_bounds__(stencil_block(TH))
+__global__ void __launch_bounds__(stencil_block(TH)) __attribute__((amdgpu_waves_per_eu(4)))
 k_back_batch(const BatchFrame *frames, const int *tile_off, const int *tile_frame, int n,
              int *counter)
 {
@@ -347,7 +394,8 @@ constexpr Inst kInst[] = {
     {0, 1, 16, kfn<0, 1, 16>()}, {0, 1, 32, kfn<0, 1, 32>()},
     {0, 2, 16, kfn<0, 2, 16>()}, {0, 2, 32, kfn<0, 2, 32>()},
     {0, 3, 16, kfn<0, 3, 16>()}, {0, 3, 32, kfn<0, 3, 32>()},
-    {0, 4, 8, kfn<0, 4, 8>()},   {0, 4, 16, kfn<0, 4, 16>()}, {0, 4, 32, kfn<0, 4, 32>()},
+    {0, 4, 8, kfn<0, 4, 8>()},   {0, 4, 16, kfn<0, 4, 16>()}, {0, 4, 24, kfn<0, 4, 24>()},
+    {0, 4, 32, kfn<0, 4, 32>()},
     {0, 7, 8, kfn<0, 7, 8>()},   {0, 7, 16, kfn<0, 7, 16>()}, {0, 7, 32, kfn<0, 7, 32>()},
     {0, 10, 8, kfn<0, 10, 8>()}, {0, 10, 16, kfn<0, 10, 16>()},
     {0, 15, 8, kfn<0, 15, 8>()}, {0, 15, 16, kfn<0, 15, 16>()},
@@ -373,7 +421,8 @@ using BatchFn = void (*)(const BatchFrame *, const int *, const int *, int, int 
 struct BatchInst { int rg, th; BatchFn fn; };
 constexpr BatchInst kBatchInst[] = {
     {1, 16, &k_back_batch<1, 16>}, {2, 16, &k_back_batch<2, 16>}, {3, 16, &k_back_batch<3, 16>},
-    {4, 8, &k_back_batch<4, 8>},   {4, 16, &k_back_batch<4, 16>}, {4, 32, &k_back_batch<4, 32>},
+    {4, 8, &k_back_batch<4, 8>},   {4, 16, &k_back_batch<4, 16>}, {4, 24, &k_back_batch<4, 24>},
+    {4, 32, &k_back_batch<4, 32>},
     {7, 8, &k_back_batch<7, 8>},   {7, 16, &k_back_batch<7, 16>}, {10, 8, &k_back_batch<10, 8>},
     {10, 16, &k_back_batch<10, 16>}, {15, 8, &k_back_batch<15, 8>}, {22, 4, &k_back_batch<22, 4>},
     {30, 4, &k_back_batch<30, 4>},

@@ -131,7 +131,7 @@ hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H
 {
     *chosen = 0;
     std::vector<int> cands;
-    for (int th : {4, 8, 16, 32})
+    for (int th : {4, 8, 16, 24, 32})
         if (stencil_has_instance(rf, rg, th) && stencil_lds_bytes(rf, rg, th) <= 160 * 1024)
             cands.push_back(th);
     if (cands.empty()) return hipSuccess;
