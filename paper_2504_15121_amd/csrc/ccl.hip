@@ -181,18 +181,18 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
     __syncthreads();
 
     const int gx = x0 + lane;
-    if (a.dn) {
-        for (int ly = wave; ly < kCH; ly += kFrontWaves) {
-            const int gy = y0 + ly;
-            if (gx >= a.W || gy >= a.H) continue;
-            const float *p = sIn + (ly + RF) * inW + lane + RF;
-            float out = __builtin_nanf("");
-            if (p[0] > 0.0f) out = RF == 1 ? filter3x3(p, inW, a.need_f) : p[0];
-            a.dn[(int64_t)gy * a.ld_dn + gx] = out;
-        }
-    }
-
+    auto filter_row = [&](int ly) {
+        const int gy = y0 + ly;
+        if (gx >= a.W || gy >= a.H) return;
+        const float *p = sIn + (ly + RF) * inW + lane + RF;
+        float out = __builtin_nanf("");
+        if (p[0] > 0.0f) out = RF == 1 ? filter3x3(p, inW, a.need_f) : p[0];
+        a.dn[(int64_t)gy * a.ld_dn + gx] = out;
+    };
     auto val = [&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; };
+    if (a.dn)
+        for (int ly = wave; ly < kCH; ly += kFrontWaves) filter_row(ly);
+
     if (CREASE) {
         const float *n = sm.nrm;
         constexpr int P = kCH * kCW;

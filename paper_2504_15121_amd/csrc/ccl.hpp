@@ -137,15 +137,16 @@ struct BitTileEdges {
     }
 };
 
-// Local labelling of one kCW x kCH tile with the edges of E.  Wave `wave` of
-// `nwaves` takes every nwaves-th row.  Horizontal edges come from a 64-bit ballot
-// and give the row runs (first pixel = initial root); vertical edges are united
-// with atomicMin hooking except where the edge at lane-1 already joins the same
-// two runs.
-// On return (after a barrier) par[] holds a local forest over ly*kCW + lane.
+// Local labelling of one kCW x kCH tile with the edges of E, in two phases that
+// each take every nwaves-th row starting at `wave`: forest_runs gives the row
+// runs from a 64-bit ballot of the horizontal edges (the first pixel of a run is
+// its initial root); after a barrier, forest_unions unites the vertical edges
+// with atomicMin hooking, except where the edge at lane-1 already joins the same
+// two runs.  After a second barrier par[] holds a local forest over
+// ly*kCW + lane.
 template <class Edges>
-__device__ __forceinline__ void local_forest(const Edges &E, int *par, unsigned long long *hmask,
-                                             int lane, int wave, int nwaves)
+__device__ __forceinline__ void forest_runs(const Edges &E, int *par, unsigned long long *hmask,
+                                            int lane, int wave, int nwaves)
 {
     for (int ly = wave; ly < kCH; ly += nwaves) {
         const bool ok = E.ok(ly, lane);
@@ -155,13 +156,28 @@ __device__ __forceinline__ void local_forest(const Edges &E, int *par, unsigned 
         par[ly * kCW + lane] = ok ? ly * kCW + run_start(vb & ~hb, lane) : -1;
         if (lane == 0) hmask[ly] = hb;
     }
-    __syncthreads();
+}
+
+template <class Edges>
+__device__ __forceinline__ void forest_unions(const Edges &E, int *par,
+                                              const unsigned long long *hmask, int lane, int wave,
+                                              int nwaves)
+{
     for (int ly = 1 + wave; ly < kCH; ly += nwaves) {
         const bool e = E.up(ly, lane);
         const unsigned long long eb = __ballot(e);
         const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
         if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);
     }
+}
+
+template <class Edges>
+__device__ __forceinline__ void local_forest(const Edges &E, int *par, unsigned long long *hmask,
+                                             int lane, int wave, int nwaves)
+{
+    forest_runs(E, par, hmask, lane, wave, nwaves);
+    __syncthreads();
+    forest_unions(E, par, hmask, lane, wave, nwaves);
     __syncthreads();
 }
 
