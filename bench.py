@@ -715,13 +715,16 @@ def main():
     # launches over the rotating sets between two HIP events on the stream the
     # kernels run on, each launch on a set whose part 1 has just left an
     # unresolved label forest (as in a step), so every launch does the step's
-    # full work
+    # full work.  The part-1 launches stay queued ahead of the first event: the
+    # host submits the burst while the GPU still runs them, so the events time
+    # the launches and their dispatch gaps, not the host's submission of the
+    # first launch to an idle GPU.
     n_rep = 4
     kern_total = 0.0
     for _ in range(n_rep):
+        torch.cuda.synchronize()
         for s in sets:
             part(s, snx.PART_FOREST)
-        torch.cuda.synchronize()
         b0 = torch.cuda.Event(enable_timing=True)
         b1 = torch.cuda.Event(enable_timing=True)
         b0.record()
@@ -742,7 +745,8 @@ def main():
                 "kernel": f"k_stencil<0,{ng // 2},{tiles[1]}> (snx_pipeline part 2)",
                 "bytes_per_px": FUSED_BYTES_PER_PX, "avg_launch_ms": round(kern_ms, 5),
                 "launch_timing": f"HIP events around {n_rep} bursts of {len(sets)} back-to-back "
-                                 "launches, each on a freshly built forest",
+                                 "launches, each on a freshly built forest, queued behind "
+                                 "the part-1 launches",
                 "in_step_ms": round(fused_ms, 5),
                 "whole_step": {"bytes_per_px": STEP_MIN_BYTES_PER_PX,
                                "bytes_note": "the method's fused minimum: 4 B disparity in, "
