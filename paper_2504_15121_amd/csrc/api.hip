@@ -573,10 +573,17 @@ static size_t plane_bytes(int32_t w, int32_t h)
     return ((size_t)w * (size_t)h * sizeof(float) + 255) / 256 * 256;
 }
 
+// Seam records of the 3x3-filter front: two int32 per tile-seam pair.
+static size_t seam_bytes(int32_t w, int32_t h)
+{
+    if (w <= 0 || h <= 0) return 0;
+    return ((size_t)snx::merge_pairs(w, h) * sizeof(int32_t) + 255) / 256 * 256;
+}
+
 size_t snx_pipeline_workspace_size(int32_t width, int32_t height)
 {
     if (!size_ok(width, height)) return 0;
-    return 256 + 2 * plane_bytes(width, height);
+    return 256 + 2 * plane_bytes(width, height) + 2 * seam_bytes(width, height);
 }
 
 snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, int32_t height,
@@ -636,10 +643,20 @@ snx_status snx_pipeline_part(const float *disp, int64_t stride, int32_t width, i
         f.ld_dn = ld_dn;
         f.forest = forest;
         f.count = num_components;
+        if (f.rf == 1 && f.dn) {
+            // the 3x3 filter's halo lets the front decide the seam pairs: the
+            // merge then reads two records per pair
+            char *sb = ws + 256 + 2 * plane_bytes(width, height);
+            f.seam_a = reinterpret_cast<int32_t *>(sb);
+            f.seam_b = reinterpret_cast<int32_t *>(sb + seam_bytes(width, height));
+        }
         if ((e = snx::launch_front(f, s)) != hipSuccess) return hip_fail(e, "snx_pipeline");
-        if ((e = snx::launch_merge(disp, stride, width, height, k_rel, t_abs, forest, s)) !=
-            hipSuccess)
-            return hip_fail(e, "snx_pipeline");
+        if (f.seam_a)
+            e = snx::launch_merge_seams(f.seam_a, f.seam_b, snx::merge_pairs(width, height),
+                                        forest, s);
+        else
+            e = snx::launch_merge(disp, stride, width, height, k_rel, t_abs, forest, s);
+        if (e != hipSuccess) return hip_fail(e, "snx_pipeline");
         if (rf > 1) {
             snx::StencilArgs a;
             if ((st = fill_stencil(a, disp, stride, width, height, rf, 0, need_f(denoise), 0,

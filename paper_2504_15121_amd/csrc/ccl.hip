@@ -91,6 +91,47 @@ __device__ __forceinline__ void write_forest(const FrontArgs &a, const int *par,
     }
 }
 
+// Seam records of one tile from its halo (needs the 1-pixel halo of the 3x3
+// filter, RF = 1): wave 0 the right seam, wave 1 the left, wave 2 the bottom,
+// wave 3 the top.  A pair of the right or bottom seam needs a union when it is
+// an edge and is not implied by the previous pair along the seam (the previous
+// pair is an edge and each side of this pair is joined to its side of that one
+// inside its tile), the rule the seam merge applies; its record is then the
+// tile root of this tile's pixel.  The left and top seams record this tile's
+// roots for the neighbours' pairs.
+template <int RF>
+__device__ __forceinline__ void write_seams(const FrontArgs &a, const int *par, const float *sIn,
+                                            int x0, int y0, int bx, int by, int lane, int wave)
+{
+    constexpr int inW = kCW + 2 * RF;
+    const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
+    const int64_t nv = (int64_t)(tx - 1) * a.H;
+    auto groot = [&](int l) {
+        if (par[l] < 0) return -1;
+        const int r = lds_find(par, l);
+        return (y0 + (r >> 6)) * a.W + x0 + (r & 63);
+    };
+    auto v = [&](int ly, int lx) { return sIn[(ly + RF) * inW + lx + RF]; };
+    auto e = [&](float p, float q) { return p > 0.0f && q > 0.0f && joined(p, q, a.k_rel, a.t_abs); };
+    if (wave == 0 && bx < tx - 1 && lane < kCH && y0 + lane < a.H) {
+        const int ly = lane;
+        const bool need = e(v(ly, kCW - 1), v(ly, kCW)) &&
+                          !(ly > 0 && e(v(ly - 1, kCW - 1), v(ly - 1, kCW)) &&
+                            e(v(ly - 1, kCW - 1), v(ly, kCW - 1)) && e(v(ly - 1, kCW), v(ly, kCW)));
+        a.seam_a[(int64_t)bx * a.H + y0 + ly] = need ? groot(ly * kCW + kCW - 1) : -1;
+    } else if (wave == 1 && bx > 0 && lane < kCH && y0 + lane < a.H) {
+        a.seam_b[(int64_t)(bx - 1) * a.H + y0 + lane] = groot(lane * kCW);
+    } else if (wave == 2 && by < ty - 1 && x0 + lane < a.W) {
+        const int lx = lane;
+        const bool need = e(v(kCH - 1, lx), v(kCH, lx)) &&
+                          !(lx > 0 && e(v(kCH - 1, lx - 1), v(kCH, lx - 1)) &&
+                            e(v(kCH - 1, lx - 1), v(kCH - 1, lx)) && e(v(kCH, lx - 1), v(kCH, lx)));
+        a.seam_a[nv + (int64_t)by * a.W + x0 + lx] = need ? groot((kCH - 1) * kCW + lx) : -1;
+    } else if (wave == 3 && by > 0 && x0 + lane < a.W) {
+        a.seam_b[nv + (int64_t)(by - 1) * a.W + x0 + lane] = groot(lane);
+    }
+}
+
 template <int RF, bool CREASE = false>
 struct FrontSmem {
     static constexpr int inW = kCW + 2 * RF, inH = kCH + 2 * RF;
@@ -209,6 +250,7 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
                      par, sm.hmask, lane, wave, kFrontWaves);
     }
     write_forest(a, par, x0, y0, lane, wave);
+    if (RF == 1 && !CREASE && a.seam_a) write_seams<RF>(a, par, sIn, x0, y0, bx, by, lane, wave);
 }
 
 
@@ -378,6 +420,21 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
                n_vseams, n_hseams, i);
 }
 
+// Seam pairs from the front's seam records: only pairs that need a union do
+// any further work (one round trip for the records, then the hook).
+__global__ void __launch_bounds__(256)
+k_ccl_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs, int32_t *par)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= pairs) return;
+    int a = seam_a[i], b = seam_b[i];
+    if (a < 0 || a == b) return;
+    if (a < b) { const int t = a; a = b; b = t; }
+    const int old = atomicMin(par + a, b);
+    if (old == a) return;
+    g_union(par, old, b);
+}
+
 __global__ void __launch_bounds__(256)
 k_ccl_merge_edges(const uint8_t *f, int64_t ld, int W, int H, int32_t *par, int n_vseams,
                   int n_hseams)
@@ -531,6 +588,15 @@ hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, 
     if (pairs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ccl_merge, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s, D, ld,
                        W, H, k_rel, t_abs, forest, nv, nh, nrm, ld_nrm, plane_nrm, crease_cos);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs,
+                              int32_t *forest, hipStream_t s)
+{
+    if (pairs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ccl_merge_seams, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s,
+                       seam_a, seam_b, pairs, forest);
     return hipGetLastError();
 }
 

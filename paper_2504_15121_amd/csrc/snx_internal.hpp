@@ -118,8 +118,15 @@ struct FrontArgs {
     double crease_cos = 0.0;
     const uint8_t *edges = nullptr;   // explicitly given edge graph (test hook), else NULL
     int64_t ld_edges = 0;
+    // Seam records (3x3-filter front only; else NULL), merge_pairs(W, H) entries
+    // each in the merge's pair order: seam_a[i] = the tile root of the pair's
+    // left/upper pixel where the pair needs a union (an edge not implied by the
+    // previous pair), else -1; seam_b[i] = the tile root of its right/lower pixel.
+    int32_t *seam_a = nullptr, *seam_b = nullptr;
 };
 hipError_t launch_front(const FrontArgs &a, hipStream_t s);
+hipError_t launch_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs,
+                              int32_t *forest, hipStream_t s);
 hipError_t launch_merge(const float *D, int64_t ld, int W, int H, double k_rel, double t_abs,
                         int32_t *forest, hipStream_t s, const float *nrm = nullptr,
                         int64_t ld_nrm = 0, int64_t plane_nrm = 0, double crease_cos = 0.0);

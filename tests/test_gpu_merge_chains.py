@@ -83,3 +83,35 @@ def test_long_merge_chains(oracle, case):
     assert cnt == nref
     assert np.array_equal(lab2, ref), (lab2 != ref).sum()
     assert cnt2 == nref
+
+
+@pytest.mark.parametrize("shape", [(37, 70), (33, 65), (64, 128), (32, 64), (1, 200), (200, 1),
+                                   (97, 193)])
+def test_pipeline_seam_records(oracle, shape):
+    """With the 3x3 filter the front decides every tile-seam pair from its halo
+    and writes seam records for the merge: labels against the oracle on seam-
+    crossing random-level frames (exact multiples of the tile, ragged, single
+    row and column), with the label forest in the labels and, with a padded
+    label stride, in the workspace."""
+    import paper_2504_15121_amd as snx
+    snx.load()
+    H, W = shape
+    rng = np.random.default_rng(H * 1000 + W)
+    cam = scenes.Camera(500.0, 500.0, 0.1, 0.5 * (W - 1), 0.5 * (H - 1))
+    for rep in range(6):
+        D = _levels(H, W, rng)
+        D[rng.random((H, W)) < (0.05, 0.3)[rep % 2]] = np.nan
+        pad = 3 * (rep % 2)
+        print(f"case seam records {shape} rep {rep} pad {pad}", flush=True)
+        d = torch.from_numpy(D).to(DEV)
+        lab = torch.full((H, W + pad), -9, dtype=torch.int32, device=DEV)
+        cnt = torch.zeros(1, dtype=torch.int32, device=DEV)
+        pts = torch.empty((H, W, 8), device=DEV)
+        ws = torch.empty(snx.snx_pipeline_workspace_size(W, H), dtype=torch.uint8, device=DEV)
+        snx.snx_pipeline(d, cam, lab[:, :W], pts, ws, num_components=cnt, filter_window=3,
+                         normal_window=3, k_rel=0.0, t_abs=1.0)
+        torch.cuda.synchronize()
+        ref, nref = oracle.components(D, 0.0, 1.0)
+        got = lab[:, :W].cpu().numpy()
+        assert np.array_equal(got, ref), (rep, (got != ref).sum())
+        assert int(cnt.item()) == nref
