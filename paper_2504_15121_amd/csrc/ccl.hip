@@ -421,15 +421,33 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
 }
 
 // Seam pairs from the front's seam records: only pairs that need a union do
-// any further work (one round trip for the records, then the hook).
+// any further work (one round trip for the records, then the hook).  Pairs of
+// one seam are consecutive threads, and a seam often joins the same two tile
+// roots at several pairs that the implied-pair rule does not catch: within a
+// wave only the first pair of each distinct root pair is united (the others
+// would only find the roots already joined, after contending for them).
 __global__ void __launch_bounds__(256)
 k_ccl_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs, int32_t *par)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= pairs) return;
-    int a = seam_a[i], b = seam_b[i];
-    if (a < 0 || a == b) return;
+    int a = -1, b = -1;
+    if (i < pairs) {
+        a = seam_a[i];
+        b = seam_b[i];
+    }
+    bool act = a >= 0 && a != b;
     if (a < b) { const int t = a; a = b; b = t; }
+    const int lane = threadIdx.x & 63;
+    bool lead = false;
+    unsigned long long m = __ballot(act);
+    while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        const int la = __builtin_amdgcn_readlane(a, l), lb = __builtin_amdgcn_readlane(b, l);
+        const bool same = act && a == la && b == lb;
+        lead = lead || lane == l;
+        m &= ~__ballot(same);
+    }
+    if (!lead) return;
     const int old = atomicMin(par + a, b);
     if (old == a) return;
     g_union(par, old, b);
