@@ -9,6 +9,11 @@
 //   [cnn    learned filter: the fused network over the tiles of every frame]
 //   back    persistent workgroups fetch (frame, tile) items: gradients, A,
 //           normals, label resolution, point records
+//
+// A plan of one frame with the LSQ filter runs the single-frame kernels
+// instead (front, seam merge from the front's seam records, fused back
+// stencil): with no other frame to fill the chip, the work-list claims and the
+// reset launch would only lengthen the frame's latency chain.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -38,6 +43,8 @@ struct snx_plan {
     int64_t *d_seam_off = nullptr;
     int64_t seam_total = 0;
     int grid_front = 1, grid_back = 1;
+    bool direct = false;                            // one frame: single-frame kernels
+    int32_t *seam_a = nullptr, *seam_b = nullptr;   // its seam records (3x3 filter)
     std::vector<void *> owned;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -71,7 +78,20 @@ void release(snx_plan *p)
 
 hipError_t enqueue(snx_plan *p, hipStream_t s)
 {
-    hipError_t e = snx::launch_batch_reset(p->d_counters, 2, p->d_frames, p->n, s);
+    hipError_t e;
+    if (p->direct) {
+        const snx::BatchFrame &b = p->host[0];
+        snx::FrontArgs f = b.front;          // the front zeroes the component count
+        f.seam_a = p->seam_a;
+        f.seam_b = p->seam_b;
+        if ((e = snx::launch_front(f, s)) != hipSuccess) return e;
+        e = f.seam_a ? snx::launch_merge_seams(f.seam_a, f.seam_b, snx::merge_pairs(f.W, f.H),
+                                               f.forest, s)
+                     : snx::launch_merge(f.D, f.ld, f.W, f.H, f.k_rel, f.t_abs, f.forest, s);
+        if (e != hipSuccess) return e;
+        return snx::launch_stencil(b.back, s);
+    }
+    e = snx::launch_batch_reset(p->d_counters, 2, p->d_frames, p->n, s);
     if (e != hipSuccess) return e;
     // the front filters with window 3 also for the learned filter (its mu)
     if ((e = snx::launch_batch_front(p->d_frames, p->d_front_off, p->d_front_frame, p->n,
@@ -284,6 +304,18 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
         return api_hip_fail(e, "snx_plan_create");
     }
     p->seam_total = soff[n];
+    p->direct = !cnn && n == 1;
+    if (p->direct && p->rf == 1 && soff[1] > 0) {
+        void *q = nullptr;
+        e = hipMalloc(&q, sizeof(int32_t) * 2 * (size_t)soff[1]);
+        if (e != hipSuccess) {
+            release(p);
+            return api_hip_fail(e, "snx_plan_create");
+        }
+        p->owned.push_back(q);
+        p->seam_a = static_cast<int32_t *>(q);
+        p->seam_b = p->seam_a + soff[1];
+    }
     int dev = 0, cus = 256;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)

@@ -243,3 +243,36 @@ def test_plan_learned_road_frames_match_oracle(oracle):
                             int(f["num_components"].item()), f["points"].cpu().numpy())
         print(f"  max normal angle {ang:.2e} rad", flush=True)
     plan.close()
+
+
+@pytest.mark.parametrize("filter_window,normal_window", [(3, 9), (1, 5)])
+def test_single_frame_plan(oracle, filter_window, normal_window):
+    """A one-frame plan runs the single-frame kernels: records against the oracle
+    and bit-identical to snx_pipeline, on the capturing run and on graph replays
+    with fresh inputs (eager work between the replays)."""
+    from tests.stagewise import check_records
+    snx = _snx()
+    sc = scenes.workload("planes_640x480")
+    f = _alloc(sc, label_pad=3 if filter_window == 1 else 0)
+    plan = snx.Plan([f], filter_window=filter_window, normal_window=normal_window)
+    cam = _cam32(sc.cam)          # the plan's camera, kept on replays with new inputs
+    st = torch.cuda.Stream()
+    for rep in range(3):
+        print(f"case single-frame plan f{filter_window} g{normal_window} rep {rep}", flush=True)
+        if rep:
+            sc = _frames([(640, 480)], 500 + rep)[0]
+            f["disp"].copy_(torch.from_numpy(sc.disp))
+            f["labels"].fill_(-9)
+            f["points"].zero_()
+            torch.cuda.synchronize()
+        with torch.cuda.stream(st):
+            plan.run(st)
+        st.synchronize()
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        del junk
+        check_records(oracle, sc.disp, cam, normal_window, f["disp_dn"].cpu().numpy(),
+                      f["labels"].cpu().numpy(), int(f["num_components"].item()),
+                      f["points"].cpu().numpy(), nf=filter_window)
+        _check(snx, [f], filter_window, normal_window)
+    plan.close()
