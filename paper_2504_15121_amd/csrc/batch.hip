@@ -44,7 +44,7 @@ struct snx_plan {
     int64_t seam_total = 0;
     int grid_front = 1, grid_back = 1;
     bool direct = false;                            // one frame: single-frame kernels
-    int32_t *seam_a = nullptr, *seam_b = nullptr;   // its seam records (3x3 filter)
+    int32_t *seam_a = nullptr, *seam_b = nullptr;   // seam records (fronts with the 3x3 halo)
     std::vector<void *> owned;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -99,7 +99,7 @@ hipError_t enqueue(snx_plan *p, hipStream_t s)
         hipSuccess)
         return e;
     if ((e = snx::launch_batch_merge(p->d_frames, p->d_seam_off, p->d_merge_frame, p->n,
-                                     p->seam_total, s)) != hipSuccess)
+                                     p->seam_total, s, p->seam_a, p->seam_b)) != hipSuccess)
         return e;
     if (p->cnn &&
         (e = snx::cnn_forward_fused_batch(p->cnn_common, p->d_cnn, p->d_cnn_off, p->d_cnn_frame,
@@ -285,6 +285,21 @@ snx_status snx_plan_create(const snx_frame *frames, int32_t n, const snx_denoise
                           hipMemcpyHostToDevice);
         p->cnn_total = coff[n];
         p->cnn_common = cnn_args[0];
+    }
+    // seam records: every front with the 3x3 halo (LSQ window 3, and the learned
+    // filter's mu) decides its seam pairs; one-frame plans allocate theirs below
+    if (e == hipSuccess && !(!cnn && n == 1) && (cnn || p->rf == 1) && soff[n] > 0) {
+        void *q = nullptr;
+        e = hipMalloc(&q, sizeof(int32_t) * 2 * (size_t)soff[n]);
+        if (e == hipSuccess) {
+            p->owned.push_back(q);
+            p->seam_a = static_cast<int32_t *>(q);
+            p->seam_b = p->seam_a + soff[n];
+            for (int i = 0; i < n; ++i) {
+                p->host[i].front.seam_a = p->seam_a + soff[i];
+                p->host[i].front.seam_b = p->seam_b + soff[i];
+            }
+        }
     }
     if (e == hipSuccess) e = hipMalloc(&p->d_frames, sizeof(snx::BatchFrame) * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_front_off, sizeof(int) * (n + 1));

@@ -420,12 +420,34 @@ __device__ __forceinline__ void merge_pair(const float *D, int64_t ld, int W, in
                n_vseams, n_hseams, i);
 }
 
+// Unites the root pairs (a, b) of the active lanes (a, b tile roots of the
+// forest par of frame f, a != b).  Pairs of one seam are consecutive threads,
+// and a seam often joins the same two tile roots at several pairs that the
+// implied-pair rule does not catch: within a wave only the first lane of each
+// distinct (frame, root pair) is united (the others would only find the roots
+// already joined, after contending for them).
+__device__ __forceinline__ void unite_root_pairs(int32_t *par, int a, int b, int f, bool act)
+{
+    if (a < b) { const int t = a; a = b; b = t; }
+    const int lane = threadIdx.x & 63;
+    bool lead = false;
+    unsigned long long m = __ballot(act);
+    while (m) {
+        const int l = __ffsll((long long)m) - 1;
+        const int la = __builtin_amdgcn_readlane(a, l), lb = __builtin_amdgcn_readlane(b, l);
+        const int lf = __builtin_amdgcn_readlane(f, l);
+        const bool same = act && a == la && b == lb && f == lf;
+        lead = lead || lane == l;
+        m &= ~__ballot(same);
+    }
+    if (!lead) return;
+    const int old = atomicMin(par + a, b);
+    if (old == a) return;
+    g_union(par, old, b);
+}
+
 // Seam pairs from the front's seam records: only pairs that need a union do
-// any further work (one round trip for the records, then the hook).  Pairs of
-// one seam are consecutive threads, and a seam often joins the same two tile
-// roots at several pairs that the implied-pair rule does not catch: within a
-// wave only the first pair of each distinct root pair is united (the others
-// would only find the roots already joined, after contending for them).
+// any further work (one round trip for the records, then the hook).
 __global__ void __launch_bounds__(256)
 k_ccl_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs, int32_t *par)
 {
@@ -435,22 +457,26 @@ k_ccl_merge_seams(const int32_t *seam_a, const int32_t *seam_b, int64_t pairs, i
         a = seam_a[i];
         b = seam_b[i];
     }
-    bool act = a >= 0 && a != b;
-    if (a < b) { const int t = a; a = b; b = t; }
-    const int lane = threadIdx.x & 63;
-    bool lead = false;
-    unsigned long long m = __ballot(act);
-    while (m) {
-        const int l = __ffsll((long long)m) - 1;
-        const int la = __builtin_amdgcn_readlane(a, l), lb = __builtin_amdgcn_readlane(b, l);
-        const bool same = act && a == la && b == lb;
-        lead = lead || lane == l;
-        m &= ~__ballot(same);
+    unite_root_pairs(par, a, b, 0, a >= 0 && a != b);
+}
+
+// The same over the seam records of every frame of a batch (frame f's records
+// at seam_off[f]).
+__global__ void __launch_bounds__(256)
+k_merge_batch_seams(const BatchFrame *frames, const int64_t *seam_off, const int *block_frame,
+                    int n, const int32_t *seam_a, const int32_t *seam_b)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int a = -1, b = -1, f = 0;
+    int32_t *par = nullptr;
+    if (i < seam_off[n]) {
+        f = block_frame[blockIdx.x];
+        while (seam_off[f + 1] <= i) ++f;
+        a = seam_a[i];
+        b = seam_b[i];
+        par = frames[f].front.forest;
     }
-    if (!lead) return;
-    const int old = atomicMin(par + a, b);
-    if (old == a) return;
-    g_union(par, old, b);
+    unite_root_pairs(par, a, b, f, a >= 0 && a != b);
 }
 
 __global__ void __launch_bounds__(256)
@@ -579,11 +605,16 @@ hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, con
 }
 
 hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off,
-                              const int *block_frame, int n, int64_t total, hipStream_t s)
+                              const int *block_frame, int n, int64_t total, hipStream_t s,
+                              const int32_t *seam_a, const int32_t *seam_b)
 {
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       frames, seam_off, block_frame, n);
+    if (seam_a)
+        hipLaunchKernelGGL(k_merge_batch_seams, dim3((unsigned)((total + 255) / 256)), dim3(256),
+                           0, s, frames, seam_off, block_frame, n, seam_a, seam_b);
+    else
+        hipLaunchKernelGGL(k_merge_batch, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                           frames, seam_off, block_frame, n);
     return hipGetLastError();
 }
 

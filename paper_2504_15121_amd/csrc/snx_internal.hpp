@@ -141,8 +141,11 @@ int front_tiles(int W, int H);
 int64_t merge_pairs(int W, int H);
 hipError_t launch_batch_front(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
                               int n, int rf, int *counter, int grid, hipStream_t s);
+// seam_a/seam_b: the batch's seam records (every frame's front writes them at
+// seam_off[f]), or NULL for the merge that decides the pairs itself.
 hipError_t launch_batch_merge(const BatchFrame *frames, const int64_t *seam_off,
-                              const int *block_frame, int n, int64_t total, hipStream_t s);
+                              const int *block_frame, int n, int64_t total, hipStream_t s,
+                              const int32_t *seam_a = nullptr, const int32_t *seam_b = nullptr);
 hipError_t launch_batch_back(const BatchFrame *frames, const int *tile_off, const int *tile_frame,
                              int n, int rg, int th, int *counter, int grid, hipStream_t s);
 hipError_t launch_batch_reset(int *counters, int n_counters, const BatchFrame *frames, int n,

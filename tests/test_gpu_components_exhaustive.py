@@ -7,7 +7,8 @@ counts).
   joined, two levels apart are not), so that masks and edge patterns vary
   together;
 * 256 frames of 70 x 37 (2 x 2 component tiles, so every frame has vertical and
-  horizontal tile seams) with the same level construction and 25 % invalid;
+  horizontal tile seams) with the same level construction and 25 % invalid, with
+  filter windows 1 and 3 (the latter through the front's seam records);
 * through the edge-graph hook (snx_components_from_edges), every one of the
   2^17 edge subsets of a 3 x 4 grid (all pixels present, and with random pixels
   absent), and random edge graphs on ragged frames, against the oracle's
@@ -38,7 +39,7 @@ def _frames(shape, n, rng, masks=None, invalid=0.25):
     return out
 
 
-def _run(snx, Ds):
+def _run(snx, Ds, filter_window=1):
     cam = scenes.Camera(100.0, 100.0, 0.1, 1.0, 1.0)
     bufs = []
     for D in Ds:
@@ -48,7 +49,7 @@ def _run(snx, Ds):
                          points=torch.empty((H, W, 8), device=DEV),
                          disp_dn=torch.empty((H, W), device=DEV),
                          num_components=torch.zeros(1, dtype=torch.int32, device=DEV)))
-    plan = snx.Plan(bufs, filter_window=1, normal_window=3, k_rel=0.0, t_abs=1.0)
+    plan = snx.Plan(bufs, filter_window=filter_window, normal_window=3, k_rel=0.0, t_abs=1.0)
     plan.run()
     torch.cuda.synchronize()
     plan.close()
@@ -73,13 +74,16 @@ def test_every_validity_mask_of_a_4x3_frame(oracle):
     _check(oracle, Ds, labs, cnts)
 
 
-def test_seam_crossing_frames(oracle):
+@pytest.mark.parametrize("filter_window", [1, 3])
+def test_seam_crossing_frames(oracle, filter_window):
+    """With the 3x3 filter the batch front writes seam records and the merge
+    reads them; with window 1 the merge decides the pairs itself."""
     import paper_2504_15121_amd as snx
     snx.load()
-    print("case 256 frames of 70x37", flush=True)
+    print(f"case 256 frames of 70x37, filter {filter_window}", flush=True)
     rng = np.random.default_rng(13)
     Ds = _frames((37, 70), 256, rng)
-    labs, cnts = _run(snx, Ds)
+    labs, cnts = _run(snx, Ds, filter_window)
     _check(oracle, Ds, labs, cnts)
 
 
