@@ -231,10 +231,22 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
         a.dn[(int64_t)gy * a.ld_dn + gx] = out;
     };
     auto val = [&](int ly, int ln) { return sIn[(ly + RF) * inW + ln + RF]; };
-    if (a.dn)
-        for (int ly = wave; ly < kCH; ly += kFrontWaves) filter_row(ly);
+    if (!CREASE) {
+        // the filter rows interleaved with the vertical unions: the waves of a
+        // CU then mix the filter's arithmetic with the unions' LDS round trips
+        // instead of running the two phases one after the other
+        const auto E = disp_edges(val, [](int, int, int, int) { return true; }, a.k_rel, a.t_abs);
+        forest_runs(E, par, sm.hmask, lane, wave, kFrontWaves);
+        __syncthreads();
+        for (int ly = wave; ly < kCH; ly += kFrontWaves) {
+            if (a.dn) filter_row(ly);
+            if (ly + 1 < kCH) forest_union_row(E, par, sm.hmask, lane, ly + 1);
+        }
+        __syncthreads();
+    } else {
+        if (a.dn)
+            for (int ly = wave; ly < kCH; ly += kFrontWaves) filter_row(ly);
 
-    if (CREASE) {
         const float *n = sm.nrm;
         constexpr int P = kCH * kCW;
         local_forest(disp_edges(val,
@@ -244,9 +256,6 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
                                                      n[2 * P + j], a.crease_cos);
                                 },
                                 a.k_rel, a.t_abs),
-                     par, sm.hmask, lane, wave, kFrontWaves);
-    } else {
-        local_forest(disp_edges(val, [](int, int, int, int) { return true; }, a.k_rel, a.t_abs),
                      par, sm.hmask, lane, wave, kFrontWaves);
     }
     write_forest(a, par, x0, y0, lane, wave);

@@ -158,17 +158,23 @@ __device__ __forceinline__ void forest_runs(const Edges &E, int *par, unsigned l
     }
 }
 
+// The vertical unions between rows ly - 1 and ly (1 <= ly < kCH).
+template <class Edges>
+__device__ __forceinline__ void forest_union_row(const Edges &E, int *par,
+                                                 const unsigned long long *hmask, int lane, int ly)
+{
+    const bool e = E.up(ly, lane);
+    const unsigned long long eb = __ballot(e);
+    const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
+    if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);
+}
+
 template <class Edges>
 __device__ __forceinline__ void forest_unions(const Edges &E, int *par,
                                               const unsigned long long *hmask, int lane, int wave,
                                               int nwaves)
 {
-    for (int ly = 1 + wave; ly < kCH; ly += nwaves) {
-        const bool e = E.up(ly, lane);
-        const unsigned long long eb = __ballot(e);
-        const unsigned long long implied = (eb << 1) & hmask[ly] & hmask[ly - 1];
-        if (e && !((implied >> lane) & 1ull)) lds_union(par, ly * kCW + lane, (ly - 1) * kCW + lane);
-    }
+    for (int ly = 1 + wave; ly < kCH; ly += nwaves) forest_union_row(E, par, hmask, lane, ly);
 }
 
 template <class Edges>
