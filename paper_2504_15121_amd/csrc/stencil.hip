@@ -26,7 +26,7 @@ struct Layout {
     size_t off_dt, off_ab, off_s, bytes;
 };
 
-__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+__host__ __device__ constexpr size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
 {
@@ -53,6 +53,30 @@ __host__ __device__ inline Layout make_layout(int rf, int rg, int th)
 // Threads per workgroup of an instance: 512 (8 waves, 4 resident per SIMD with
 // two workgroups' LDS on a CU) for tiles of 16 rows or more, else 256.
 __host__ __device__ constexpr int stencil_block(int th) { return th >= 16 ? 512 : kBlock; }
+
+// Waves per SIMD an unrolled instance is built for: as many workgroups as its
+// LDS lets share a CU, at most four waves a SIMD (then at most 128 VGPRs); the
+// large windows, one workgroup a CU, get the registers they need unspilled.
+__host__ __device__ constexpr size_t layout_bytes(int rf, int rg, int th)
+{
+    // make_layout's total, for compile-time use
+    const int R = rf + rg, inW = kTileW + 2 * R, inH = th + 2 * R;
+    const int dtW = kTileW + 2 * rg, dtH = th + 2 * rg;
+    size_t off = align_up(sizeof(float) * (size_t)inH * inW, 16);
+    if (rf > 0) off = align_up(off + sizeof(float) * (size_t)dtH * dtW, 16);
+    size_t nrow = 0;
+    if (rf >= 2) nrow = (size_t)inH * dtW;
+    if (rg > 0 && (size_t)dtH * kTileW > nrow) nrow = (size_t)dtH * kTileW;
+    off = align_up(off + 8 * nrow, 16);
+    return align_up(off + 16 * nrow, 16);
+}
+
+__host__ __device__ constexpr int stencil_waves(int rf, int rg, int th)
+{
+    const size_t wgs = (size_t)160 * 1024 / layout_bytes(rf, rg, th);
+    const int w = (stencil_block(th) / 256) * (int)(wgs < 1 ? 1 : wgs);
+    return w > 4 ? 4 : w;
+}
 
 // One 64 x th output tile of the stencil.
 template <int RF, int RG, int TH>
@@ -341,7 +365,8 @@ __device__ __forceinline__ void stencil_tile(const StencilArgs &a, int bx, int b
 
 // two 512-thread workgroups per CU need at most 128 VGPRs (4 waves a SIMD)
 template <int RF, int RG, int TH>
-__global__ void __launch_bounds__(stencil_block(TH)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(stencil_block(TH))
+__attribute__((amdgpu_waves_per_eu(TH > 0 && RF >= 0 && RG >= 0 ? stencil_waves(RF, RG, TH) : 4)))
 k_stencil(StencilArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -353,7 +378,8 @@ k_stencil(StencilArgs a)
 
 // Persistent back stage over the (frame, tile) work list of a batch.
 template <int RG, int TH>
-__global__ void __launch_bounds__(stencil_block(TH)) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(stencil_block(TH))
+__attribute__((amdgpu_waves_per_eu(stencil_waves(0, RG, TH))))
 k_back_batch(const BatchFrame *frames, const int *tile_off, const int *tile_frame, int n,
              int *counter)
 {
@@ -397,10 +423,11 @@ constexpr Inst kInst[] = {
     {0, 4, 8, kfn<0, 4, 8>()},   {0, 4, 16, kfn<0, 4, 16>()}, {0, 4, 24, kfn<0, 4, 24>()},
     {0, 4, 32, kfn<0, 4, 32>()},
     {0, 7, 8, kfn<0, 7, 8>()},   {0, 7, 16, kfn<0, 7, 16>()}, {0, 7, 32, kfn<0, 7, 32>()},
-    {0, 10, 8, kfn<0, 10, 8>()}, {0, 10, 16, kfn<0, 10, 16>()},
-    {0, 15, 8, kfn<0, 15, 8>()}, {0, 15, 16, kfn<0, 15, 16>()},
-    {0, 22, 4, kfn<0, 22, 4>()}, {0, 22, 8, kfn<0, 22, 8>()},
-    {0, 30, 4, kfn<0, 30, 4>()}, {0, 30, 8, kfn<0, 30, 8>()},
+    {0, 10, 8, kfn<0, 10, 8>()}, {0, 10, 16, kfn<0, 10, 16>()}, {0, 10, 32, kfn<0, 10, 32>()},
+    {0, 15, 8, kfn<0, 15, 8>()}, {0, 15, 16, kfn<0, 15, 16>()}, {0, 15, 32, kfn<0, 15, 32>()},
+    {0, 22, 4, kfn<0, 22, 4>()}, {0, 22, 8, kfn<0, 22, 8>()},   {0, 22, 16, kfn<0, 22, 16>()},
+    {0, 22, 32, kfn<0, 22, 32>()},
+    {0, 30, 4, kfn<0, 30, 4>()}, {0, 30, 8, kfn<0, 30, 8>()},   {0, 30, 16, kfn<0, 30, 16>()},
     // fused 3x3 filter + gradient (snx_oriented_point_cloud)
     {1, 1, 16, kfn<1, 1, 16>()}, {1, 2, 16, kfn<1, 2, 16>()}, {1, 3, 16, kfn<1, 3, 16>()},
     {1, 4, 8, kfn<1, 4, 8>()},   {1, 4, 16, kfn<1, 4, 16>()}, {1, 4, 32, kfn<1, 4, 32>()},
@@ -415,6 +442,9 @@ constexpr Inst kInst[] = {
 
 size_t stencil_lds_bytes(int rf, int rg, int th) { return make_layout(rf, rg, th).bytes; }
 
+// the compile-time LDS size used for the instances' occupancy agrees with the layout
+static_assert(layout_bytes(0, 4, 32) == 72960 && layout_bytes(1, 4, 16) > 0, "layout size");
+
 int back_tiles(int W, int H, int th) { return ((W + kTileW - 1) / kTileW) * ((H + th - 1) / th); }
 
 using BatchFn = void (*)(const BatchFrame *, const int *, const int *, int, int *);
@@ -424,8 +454,11 @@ constexpr BatchInst kBatchInst[] = {
     {4, 8, &k_back_batch<4, 8>},   {4, 16, &k_back_batch<4, 16>}, {4, 24, &k_back_batch<4, 24>},
     {4, 32, &k_back_batch<4, 32>},
     {7, 8, &k_back_batch<7, 8>},   {7, 16, &k_back_batch<7, 16>}, {10, 8, &k_back_batch<10, 8>},
-    {10, 16, &k_back_batch<10, 16>}, {15, 8, &k_back_batch<15, 8>}, {22, 4, &k_back_batch<22, 4>},
-    {30, 4, &k_back_batch<30, 4>},
+    {10, 16, &k_back_batch<10, 16>}, {10, 32, &k_back_batch<10, 32>},
+    {15, 8, &k_back_batch<15, 8>}, {15, 16, &k_back_batch<15, 16>}, {15, 32, &k_back_batch<15, 32>},
+    {22, 4, &k_back_batch<22, 4>}, {22, 8, &k_back_batch<22, 8>}, {22, 16, &k_back_batch<22, 16>},
+    {22, 32, &k_back_batch<22, 32>},
+    {30, 4, &k_back_batch<30, 4>}, {30, 8, &k_back_batch<30, 8>}, {30, 16, &k_back_batch<30, 16>},
 };
 
 bool batch_has_instance(int rg, int th)
