@@ -366,3 +366,53 @@ def test_tile_heights_do_not_change_outputs():
     _same(ref_o, run_oriented(sc.disp, cam, 3, 9))
     snx.snx_tune_set(W, H, 1, 9, 0)
     snx.snx_tune_set(W, H, 3, 9, 0)
+
+
+@pytest.mark.parametrize("ng", [21, 31, 45, 61])
+def test_large_window_tile_heights(oracle, ng):
+    """The large gradient windows run in tall tiles (one workgroup a CU): every
+    compiled tile height of the gradient pass gives bitwise identical results,
+    the tallest one checked against the oracle too; and a batch plan on the
+    same frame with each tile height (its persistent back stage) equals the
+    single-frame pipeline."""
+    from tests.test_gpu_batch import _check
+    snx = _snx()
+    H, W = 150, 131
+    rng = np.random.default_rng(ng)
+    cam = scenes.Camera.centred(W, H, 300.0, 0.125)
+    v, u = np.mgrid[0:H, 0:W]
+    D = (40.0 + 0.15 * u - 0.12 * v + rng.normal(0, 0.4, (H, W))).astype(np.float32)
+    D[rng.random((H, W)) < 0.07] = np.nan
+    ref = run_separate(D, cam, 1, ng)
+    tallest = None
+    try:
+        for th in (4, 8, 16, 32):
+            try:
+                snx.snx_tune_set(W, H, 1, ng, th)
+            except snx.SnxError as e:
+                assert e.status == 2, e
+                continue
+            print(f"case large window ng={ng} tile height {th}", flush=True)
+            g = run_separate(D, cam, 1, ng)
+            _same(ref, g)
+            tallest = th
+            f = dict(disp=torch.from_numpy(D).to(DEV), cam=cam,
+                     labels=torch.empty((H, W), dtype=torch.int32, device=DEV),
+                     points=torch.empty((H, W, 8), device=DEV),
+                     disp_dn=torch.empty((H, W), device=DEV),
+                     num_components=torch.zeros(1, dtype=torch.int32, device=DEV))
+            g2 = dict(f, disp=torch.from_numpy(D[::-1].copy()).to(DEV),
+                      labels=torch.empty((H, W), dtype=torch.int32, device=DEV),
+                      points=torch.empty((H, W, 8), device=DEV),
+                      disp_dn=torch.empty((H, W), device=DEV),
+                      num_components=torch.zeros(1, dtype=torch.int32, device=DEV))
+            plan = snx.Plan([f, g2], filter_window=1, normal_window=ng)
+            plan.run()
+            torch.cuda.synchronize()
+            _check(snx, [f, g2], 1, ng)
+            plan.close()
+        assert tallest is not None
+        snx.snx_tune_set(W, H, 1, ng, tallest)
+        check_parity(oracle, D, cam, 1, ng, run_separate(D, cam, 1, ng))
+    finally:
+        snx.snx_tune_set(W, H, 1, ng, 0)
