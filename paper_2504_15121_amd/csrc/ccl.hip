@@ -3,11 +3,15 @@
 //   k_front       one 64 x 32 tile per workgroup: the local forest of the tile
 //                 (ballot row runs + LDS union-find), written as the global
 //                 index of each pixel's local root; optionally the filter of the
-//                 same tile (window 1 or 3) from the same read of the disparity.
+//                 same tile (window 1 or 3) from the same read of the disparity,
+//                 and with the 3x3 filter's halo the tile's seam records (which
+//                 of its seam pairs need a union, and the tile roots involved).
 //   k_ccl_merge   one thread per tile-seam pixel pair; a pair is skipped when
 //                 the previous pair along the seam is joined and both sides are
 //                 joined to it inside their tiles (so the union is implied); the
 //                 rest are united in the global forest with atomicMin hooking.
+//   k_ccl_merge_seams  the same from the seam records (two coalesced loads a
+//                 pair, one union per distinct root pair of a wave).
 //   k_ccl_flatten every pixel follows its parent chain to the root, writes its
 //                 own label and counts roots with a wave ballot.
 //
