@@ -610,8 +610,8 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {max(args.gpus, world)}); "
-              "a multi-GPU run is not supported", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU (asked for {max(args.gpus, world)}); "
+              "multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
