@@ -42,7 +42,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
-        from . import build as _build  # compile the checker on first use
+        from . import build as _build  # compile the oracle library on first use
         _build.build()
     lib = C.CDLL(_LIB_PATH)
     lib.snxo_denoise.argtypes = [_dp, C.c_int, C.c_int, C.c_int, C.c_int, _dp]
