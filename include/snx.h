@@ -290,11 +290,11 @@ snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t he
 /* snx_compact_points_noalloc -- snx_compact_points for callers that cannot
  * allocate or pass device memory of their own (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc).  Same arguments and
- * output as snx_compact_points without the workspace: the chunk counts and
- * offsets live in a static 64 KiB device array of the library (one copy per
- * GPU, held until the process ends; its address is looked up once per device on
- * the first call there).  The call allocates nothing.  Limit: width * height <=
- * 33 554 432 records (8192 chunks of 4096); larger frames return
+ * output as snx_compact_points without the workspace: the chunk counts live in
+ * a static 32 KiB device array of the library (one copy per GPU, held until the
+ * process ends; its address is looked up once per device on the first call
+ * there).  The call allocates nothing.  Limit: width * height <= 33 554 432
+ * records (8192 chunks of 4096); larger frames return
  * SNX_ERR_UNSUPPORTED before anything is launched.  Every call on one GPU
  * shares that GPU's array: calls that overlap on one GPU (concurrent streams,
  * host threads) race and must be serialised by the caller. */

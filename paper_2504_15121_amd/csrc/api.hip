@@ -208,7 +208,7 @@ snx_status snx_affine_normals(const float *disp_dn, int64_t stride, int32_t widt
 static size_t ws_compact(int32_t w, int32_t h)
 {
     if (!size_ok(w, h)) return 0;
-    return 256 + 2 * sizeof(int32_t) * (size_t)snx::compact_chunks((int64_t)w * h);
+    return 256 + sizeof(int32_t) * (size_t)snx::compact_chunks((int64_t)w * h);
 }
 
 size_t snx_compact_points_workspace_size(int32_t width, int32_t height)
@@ -235,9 +235,9 @@ snx_status snx_compact_points(const snx_point *points, int32_t width, int32_t he
     if (pb < ob + bytes && ob < pb + bytes) return fail(SNX_ERR_ARG, "out overlaps points");
     if (!workspace || workspace_bytes < ws_compact(width, height))
         return fail(SNX_ERR_WORKSPACE, "workspace needs %zu bytes", ws_compact(width, height));
-    int32_t *cc = reinterpret_cast<int32_t *>(static_cast<char *>(workspace) + 256);
-    int32_t *co = cc + snx::compact_chunks(n);
-    hipError_t e = snx::launch_compact(points, n, out, count, cc, co, s);
+    // the chunk counts on a 256-byte boundary inside the workspace's slack
+    int32_t *cc = reinterpret_cast<int32_t *>(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    hipError_t e = snx::launch_compact(points, n, out, count, cc, s);
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points");
 }
 
@@ -260,10 +260,10 @@ snx_status snx_compact_points_noalloc(const snx_point *points, int32_t width, in
     const char *pb = reinterpret_cast<const char *>(points), *ob = reinterpret_cast<const char *>(out);
     const int64_t bytes = n * (int64_t)sizeof(snx_point);
     if (pb < ob + bytes && ob < pb + bytes) return fail(SNX_ERR_ARG, "out overlaps points");
-    int32_t *cc = nullptr, *co = nullptr;
-    hipError_t e = snx::compact_noalloc_scratch(&cc, &co);
+    int32_t *cc = nullptr;
+    hipError_t e = snx::compact_noalloc_scratch(&cc);
     if (e != hipSuccess) return hip_fail(e, "snx_compact_points_noalloc (scratch address)");
-    e = snx::launch_compact(points, n, out, count, cc, co, s);
+    e = snx::launch_compact(points, n, out, count, cc, s);
     return e == hipSuccess ? SNX_OK : hip_fail(e, "snx_compact_points_noalloc");
 }
 

@@ -62,12 +62,13 @@ hipError_t autotune_stencil(int rf, int rg, int need_f, int need_g, int W, int H
 
 // Compacted point cloud (compact.hip): the defined records in raster order.
 int64_t compact_chunks(int64_t n);
+// chunk_count: compact_chunks(n) entries of device scratch
 hipError_t launch_compact(const snx_point *in, int64_t n, snx_point *out, int32_t *count,
-                          int32_t *chunk_count, int32_t *chunk_off, hipStream_t s);
+                          int32_t *chunk_count, hipStream_t s);
 // Allocation-free variant: the largest record count it takes, and this device's
-// scratch (chunk counts, chunk offsets) in the library's static device array.
+// chunk counts in the library's static device array.
 int64_t compact_noalloc_max_records();
-hipError_t compact_noalloc_scratch(int32_t **chunk_count, int32_t **chunk_off);
+hipError_t compact_noalloc_scratch(int32_t **chunk_count);
 
 // Component-restricted gradient window (restricted.hip): the n_g window keeps
 // only the valid pixels whose label equals the centre's.

@@ -101,7 +101,8 @@ def test_affine_normals_validation(lib):
 
 def test_compact_validation(lib):
     cnt = FAKE
-    assert lib.snx_compact_points_workspace_size(1920, 1080) == 256 + 8 * ((1920 * 1080 + 4095) // 4096)
+    # 256 bytes of alignment slack, then one int32 count per 4096-record chunk
+    assert lib.snx_compact_points_workspace_size(1920, 1080) == 256 + 4 * ((1920 * 1080 + 4095) // 4096)
     ws = lib.snx_compact_points_workspace_size(64, 64)
     assert lib.snx_compact_points(FAKE, 64, 64, FAKE, None, FAKE, ws, None) == 1       # no count
     assert lib.snx_compact_points(None, 64, 64, FAKE, cnt, FAKE, ws, None) == 1

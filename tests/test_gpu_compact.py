@@ -70,3 +70,36 @@ def test_compact_none_and_all_defined(oracle):
     f = np.where((np.arange(H * W) % 3) == 1, 1, 0).astype(np.uint32).reshape(H, W)
     rec[..., 7] = f.view(np.float32)
     assert _check(oracle, snx, torch.from_numpy(rec).to(DEV)) == int(f.sum())
+
+
+def test_compact_many_chunks_and_repeated_calls(oracle):
+    """More chunks than one wave of the chip's workgroups (6 M records, about
+    2900 chunks), with the defined records' density changing from region to
+    region (long empty and long full stretches, so a chunk's walk back over the
+    earlier chunks' counts crosses many chunks); then the same workspace reused
+    by calls on smaller and larger inputs, each bit-exact."""
+    snx = _snx()
+    rng = np.random.default_rng(11)
+    H, W = 2000, 3000
+    print(f"case compact many chunks {W}x{H}", flush=True)
+    rec = rng.normal(size=(H, W, 8)).astype(np.float32)
+    dens = np.repeat(rng.choice([0.0, 0.02, 0.5, 0.97, 1.0], size=H // 50), 50)
+    f = ((rng.random((H, W)) < dens[:, None]).astype(np.uint32)
+         | (rng.random((H, W)) < 0.5).astype(np.uint32) * np.uint32(2))
+    rec[..., 7] = f.view(np.float32)
+    pts = torch.from_numpy(rec).to(DEV)
+    assert _check(oracle, snx, pts) == int((f & 1).sum())
+    ws = torch.empty(snx.snx_compact_points_workspace_size(W, H), dtype=torch.uint8, device=DEV)
+    for h, w in [(7, 300), (H, W), (1, 1), (1000, 1500)]:
+        print(f"case compact reuse {w}x{h}", flush=True)
+        sub = pts[:h, :w].contiguous()
+        out = torch.full((h * w, 8), -3.0, device=DEV)
+        cnt = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+        snx.snx_compact_points(sub, out, cnt, ws)
+        torch.cuda.synchronize()
+        ref = oracle.compact_points(rec[:h, :w])
+        n = int(cnt.item())
+        assert n == ref.shape[0]
+        o = out.cpu().numpy()
+        assert np.array_equal(o[:n].view(np.uint32), ref.view(np.uint32))
+        assert np.all(o[n:] == -3.0)
