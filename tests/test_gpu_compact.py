@@ -73,11 +73,11 @@ def test_compact_none_and_all_defined(oracle):
 
 
 def test_compact_many_chunks_and_repeated_calls(oracle):
-    """More chunks than one wave of the chip's workgroups (6 M records, about
-    2900 chunks), with the defined records' density changing from region to
-    region (long empty and long full stretches, so a chunk's walk back over the
-    earlier chunks' counts crosses many chunks); then the same workspace reused
-    by calls on smaller and larger inputs, each bit-exact."""
+    """6 M records (about 1500 chunks of 4096: more count workgroups than fit
+    on the chip at once, and chunk offsets summed over many earlier chunks),
+    with the defined records' density changing from region to region (long
+    empty and long full stretches); then the same workspace reused by calls on
+    smaller and larger inputs, each bit-exact."""
     snx = _snx()
     rng = np.random.default_rng(11)
     H, W = 2000, 3000
