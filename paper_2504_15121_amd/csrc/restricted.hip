@@ -5,11 +5,16 @@
 // covered-depth predicate).  One 64 x 16 output tile per 256-thread workgroup.
 //
 // The mask depends on the centre's label, so the window sums are not
-// separable: each centre walks its window in LDS (validity-coded D~ and the
-// labels, halo r), one row at a time; a row's integer moments and its two data
-// sums (exact FP64 sums of float32 values times small integers) are combined
-// into the column moments with the row offset.  The solve, A and normal are the
-// square-window ones.
+// separable in general: each centre walks its window in LDS (validity-coded D~
+// and the labels, halo r), one row at a time; a row's integer moments and its
+// two data sums (exact FP64 sums of float32 values times small integers) are
+// combined into the column moments with the row offset.  Each wave owns four
+// consecutive output rows; where every valid pixel that its windows reach
+// carries one label, the mask of every centre there is the plain validity
+// mask, and the wave takes the separable route instead: per column, the row
+// moments of its 2r + 1 rows summed once, then the window slid down a row at a
+// time.  Every sum is exact either way, so both routes give the same numbers.
+// The solve, A and normal are the square-window ones.
 #include "lsq.hpp"
 
 namespace snx {
@@ -44,8 +49,114 @@ k_affine_labels(RestrictArgs a)
     }
     __syncthreads();
 
-    const int tx = tid & 63;
-    for (int ty = tid >> 6; ty < kRsH; ty += kRsBlock / 64) {
+    const int tx = tid & 63, wave = tid >> 6;
+    constexpr int kRows = kRsH / (kRsBlock / 64);   // output rows per wave
+    const int ty0 = kRows * wave;
+    auto output = [&](int ty, float a1, float a2, float nx, float ny, float nz) {
+        const int64_t o = (int64_t)(y0 + ty) * a.ld_out + x0 + tx;
+        if (a.aff) {
+            a.aff[o] = a1;
+            a.aff[o + a.plane_out] = a2;
+        }
+        if (a.nrm) {
+            a.nrm[o] = nx;
+            a.nrm[o + a.plane_out] = ny;
+            a.nrm[o + 2 * a.plane_out] = nz;
+        }
+    };
+    // one label among the valid pixels of LDS rows ty0 .. ty0 + kRows - 1 + 2r
+    // (every window of this wave's outputs)?
+    int lmin = 0x7fffffff, lmax = -0x7fffffff - 1;
+    for (int ly = ty0; ly < ty0 + kRows + 2 * r && ly < LH; ++ly)
+        for (int lx = tx; lx < LW; lx += 64) {
+            const int e = ly * LW + lx;
+            if (sD[e] > 0.0f) {
+                lmin = min(lmin, sL[e]);
+                lmax = max(lmax, sL[e]);
+            }
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lmin = min(lmin, __shfl_xor(lmin, o));
+        lmax = max(lmax, __shfl_xor(lmax, o));
+    }
+    __shared__ int s_mixed[kRsBlock / 64], s_next;
+    if (tx == 0) s_mixed[wave] = lmin < lmax;
+    if (tid == 0) s_next = 0;
+    __syncthreads();
+    const bool gx_in = x0 + tx < a.W;
+    if (lmin >= lmax) {
+        // separable route: row moments of LDS row ly for this column's window
+        auto rowm = [&](int ly) { return row_moments<(RC > 0 ? RC : -1)>(sD + ly * LW + tx, r); };
+        ColMom m;
+        m.N = m.Sx = m.Sy = m.Sxx = m.Sxy = m.Syy = 0;
+        m.R0 = m.Rx = m.Ry = 0.0;
+        for (int dy = -r; dy <= r; ++dy) {
+            const RowMom q = rowm(ty0 + r + dy);
+            const int c0 = q.a & 0xffff, c1 = (q.a >> 16) - kColOff;
+            m.N += c0;
+            m.Sx += c1;
+            m.Sy += dy * c0;
+            m.Sxx += q.b;
+            m.Sxy += dy * c1;
+            m.Syy += dy * dy * c0;
+            m.R0 += q.s0;
+            m.Rx += q.s1;
+            m.Ry += (double)dy * q.s0;
+        }
+#pragma unroll
+        for (int h = 0; h < kRows; ++h) {
+            const int ty = ty0 + h;
+            if (h > 0) {
+                // drop the window's top row, add the next one below, re-centre
+                const RowMom qo = rowm(ty - 1), qn = rowm(ty + 2 * r);
+                const int c0o = qo.a & 0xffff, c1o = (qo.a >> 16) - kColOff;
+                const int c0n = qn.a & 0xffff, c1n = (qn.a >> 16) - kColOff;
+                ColMom u;
+                u.N = m.N - c0o + c0n;
+                u.Sx = m.Sx - c1o + c1n;
+                u.Sxx = m.Sxx - qo.b + qn.b;
+                const int t0 = m.Sy + r * c0o + (r + 1) * c0n;
+                u.Sy = t0 - u.N;
+                u.Syy = (m.Syy - r * r * c0o + (r + 1) * (r + 1) * c0n) - 2 * t0 + u.N;
+                u.Sxy = (m.Sxy + r * c1o + (r + 1) * c1n) - u.Sx;
+                u.R0 = (m.R0 - qo.s0) + qn.s0;
+                u.Rx = (m.Rx - qo.s1) + qn.s1;
+                u.Ry = ((m.Ry + (double)r * qo.s0) + (double)(r + 1) * qn.s0) - u.R0;
+                m = u;
+            }
+            if (!gx_in || y0 + ty >= a.H) continue;
+            const int pc = (ty + r) * LW + tx + r;
+            const float Dc = sD[pc];
+            float nx = __builtin_nanf(""), ny = nx, nz = nx, a1 = nx, a2 = nx;
+            if (Dc > 0.0f && sL[pc] >= 0) {
+                double gu, gv;
+                if (slope_solve(m, Dc, a.need_g, gu, gv)) {
+                    a1 = (float)(1.0 - gu);
+                    a2 = (float)(-gv);
+                    normal_from_slope(gu, gv, Dc, x0 + tx, y0 + ty, a.fx, a.fy, a.u0, a.v0, nx,
+                                      ny, nz);
+                }
+            }
+            output(ty, a1, a2, nx, ny, nz);
+        }
+    }
+    // The rows of the mixed bands are shared out row by row from an LDS
+    // counter, so a wave that has finished its own band takes on the rows of
+    // the others' instead of idling beside them.
+    int mixed_rows = 0;
+#pragma unroll
+    for (int w = 0; w < kRsBlock / 64; ++w) mixed_rows += s_mixed[w] ? kRows : 0;
+    while (true) {
+        int i = 0;
+        if (tx == 0) i = atomicAdd(&s_next, 1);
+        i = __shfl(i, 0);
+        if (i >= mixed_rows) break;
+        // row i % kRows of the (i / kRows)-th mixed band
+        int band = -1;
+        for (int k = i / kRows; k >= 0; --k)
+            do ++band; while (!s_mixed[band]);
+        const int ty = kRows * band + i % kRows;
         const int gx = x0 + tx, gy = y0 + ty;
         if (gx >= a.W || gy >= a.H) continue;
         const int pc = (ty + r) * LW + tx + r;
@@ -96,16 +207,7 @@ k_affine_labels(RestrictArgs a)
                 normal_from_slope(gu, gv, Dc, gx, gy, a.fx, a.fy, a.u0, a.v0, nx, ny, nz);
             }
         }
-        const int64_t o = (int64_t)gy * a.ld_out + gx;
-        if (a.aff) {
-            a.aff[o] = a1;
-            a.aff[o + a.plane_out] = a2;
-        }
-        if (a.nrm) {
-            a.nrm[o] = nx;
-            a.nrm[o + a.plane_out] = ny;
-            a.nrm[o + 2 * a.plane_out] = nz;
-        }
+        output(ty, a1, a2, nx, ny, nz);
     }
 }
 

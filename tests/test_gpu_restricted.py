@@ -108,3 +108,31 @@ def test_restricted_one_component_equals_plain_window(oracle):
     assert np.array_equal(np.isnan(pa), np.isnan(ga))
     m = np.isfinite(pa)
     assert np.abs(pa[m].astype(np.float64) - ga[m]).max() <= 2.0 ** -21 * np.abs(pa[m]).max()
+
+
+def test_restricted_uniform_and_mixed_bands(oracle):
+    """Each wave of the kernel owns four output rows of a 64 x 16 tile and takes
+    the separable route where every valid pixel its windows reach carries one
+    label; the rows of the other bands are shared among the tile's waves.  One
+    plane, one label, with single pixels of a second label placed so that tiles
+    hold one, two, three or all four mixed bands, and a block of valid pixels
+    labelled -1 (no component: undefined outputs there): every route and every
+    sharing of rows against the oracle."""
+    print("case restricted uniform and mixed bands", flush=True)
+    H, W = 64, 260
+    v, u = np.mgrid[0:H, 0:W].astype(np.float64)
+    D = (30.0 + 0.05 * u - 0.03 * v).astype(np.float32)
+    D[5, 7] = np.nan
+    lab = np.zeros((H, W), np.int32)
+    # foreign labels in tile columns 0-3; with windows 3, 9 and 15 the tiles
+    # hold from none to all four mixed bands
+    lab[1, 20] = 7
+    lab[2, 80] = 7
+    lab[9, 90] = 7
+    lab[24, 150] = 9
+    lab[32, 200:205] = 11
+    # valid pixels without a component
+    lab[48:60, 230:250] = -1
+    cam = scenes.Camera(300.0, 300.0, 0.2, 130.0, 32.0)
+    for ng in (3, 9, 15):
+        _check(oracle, D, lab, cam, ng)
