@@ -19,6 +19,8 @@
 // retried from the value the atomic returned.  After the merge a pixel's entry
 // only ever changes to its root, so ordinary loads that see an older value still
 // lead to the right root.
+#include <atomic>
+
 #include "ccl.hpp"
 #include "lsq.hpp"
 
@@ -79,10 +81,10 @@ __device__ __forceinline__ void g_union(int32_t *par, int a, int b)
 // The tile's local forest as global indices of each pixel's local root (-1 for
 // an invalid pixel).
 __device__ __forceinline__ void write_forest(const FrontArgs &a, const int *par, int x0, int y0,
-                                             int lane, int wave)
+                                             int lane, int wave, int nwaves = kFrontWaves)
 {
     const int gx = x0 + lane;
-    for (int ly = wave; ly < kCH; ly += kFrontWaves) {
+    for (int ly = wave; ly < kCH; ly += nwaves) {
         const int gy = y0 + ly;
         if (gx >= a.W || gy >= a.H) continue;
         const int l = ly * kCW + lane;
@@ -145,9 +147,9 @@ struct FrontSmem {
     float nrm[CREASE ? 3 * kCH * kCW : 1];    // crease-aware: the tile's normals
 };
 
-// One 64 x 32 tile: filter (window 1 or 3) and local component forest
-// (crease-aware with CREASE: every edge also passes crease_ok).
-template <int RF, bool CREASE = false>
+// One 64 x 32 tile by NW waves: filter (window 1 or 3) and local component
+// forest (crease-aware with CREASE: every edge also passes crease_ok).
+template <int RF, bool CREASE = false, int NW = kFrontWaves>
 __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
                                            FrontSmem<RF, CREASE> &sm)
 {
@@ -162,7 +164,7 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
     // row as 16 aligned 16-byte loads and the two halo columns as single floats
     // (no sector is fetched for a one-float overhang); other tiles read element
     // by element.
-    constexpr int NTH = kFrontWaves * 64;
+    constexpr int NTH = NW * 64;
     const int tid = threadIdx.x;
     if (x0 + kCW <= a.W && (a.ld & 3) == 0 && ((uintptr_t)a.D & 15) == 0) {
         constexpr int NB4 = inH * (kCW / 4), NL4 = (NB4 + NTH - 1) / NTH;
@@ -215,7 +217,7 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
         }
     }
     if (CREASE) {
-        for (int e = threadIdx.x; e < 3 * kCH * kCW; e += kFrontWaves * 64) {
+        for (int e = threadIdx.x; e < 3 * kCH * kCW; e += NW * 64) {
             const int c = e / (kCH * kCW), l = e - c * (kCH * kCW);
             const int gy = y0 + (l >> 6), gxx = x0 + (l & 63);
             float n = __builtin_nanf("");
@@ -240,16 +242,16 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
         // CU then mix the filter's arithmetic with the unions' LDS round trips
         // instead of running the two phases one after the other
         const auto E = disp_edges(val, [](int, int, int, int) { return true; }, a.k_rel, a.t_abs);
-        forest_runs(E, par, sm.hmask, lane, wave, kFrontWaves);
+        forest_runs(E, par, sm.hmask, lane, wave, NW);
         __syncthreads();
-        for (int ly = wave; ly < kCH; ly += kFrontWaves) {
+        for (int ly = wave; ly < kCH; ly += NW) {
             if (a.dn) filter_row(ly);
             if (ly + 1 < kCH) forest_union_row(E, par, sm.hmask, lane, ly + 1);
         }
         __syncthreads();
     } else {
         if (a.dn)
-            for (int ly = wave; ly < kCH; ly += kFrontWaves) filter_row(ly);
+            for (int ly = wave; ly < kCH; ly += NW) filter_row(ly);
 
         const float *n = sm.nrm;
         constexpr int P = kCH * kCW;
@@ -260,9 +262,9 @@ __device__ __forceinline__ void front_tile(const FrontArgs &a, int bx, int by,
                                                      n[2 * P + j], a.crease_cos);
                                 },
                                 a.k_rel, a.t_abs),
-                     par, sm.hmask, lane, wave, kFrontWaves);
+                     par, sm.hmask, lane, wave, NW);
     }
-    write_forest(a, par, x0, y0, lane, wave);
+    write_forest(a, par, x0, y0, lane, wave, NW);
     if (RF == 1 && !CREASE && a.seam_a) write_seams<RF>(a, par, sIn, x0, y0, bx, by, lane, wave);
 }
 
@@ -287,15 +289,17 @@ k_front_edges(FrontArgs a)
     write_forest(a, par, x0, y0, lane, wave);
 }
 
-template <int RF, bool CREASE>
-__global__ void __launch_bounds__(kFrontWaves * 64)
+// NW = 16 (two rows a wave) for frames of no more tiles than the chip has CUs,
+// where each tile's own critical path is the kernel's time.
+template <int RF, bool CREASE, int NW = kFrontWaves>
+__global__ void __launch_bounds__(NW * 64)
 k_front(FrontArgs a)
 {
     __shared__ FrontSmem<RF, CREASE> sm;
     if (a.count && blockIdx.x == 0 && threadIdx.x == 0) *a.count = 0;
     const int tx = (a.W + kCW - 1) / kCW, ty = (a.H + kCH - 1) / kCH;
     const int t = xcd_tile(blockIdx.x, tx * ty);
-    front_tile<RF, CREASE>(a, t % tx, t / tx, sm);
+    front_tile<RF, CREASE, NW>(a, t % tx, t / tx, sm);
 }
 
 // Persistent front over the (frame, tile) work list of a batch: workgroups
@@ -579,16 +583,44 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// Compute units of the current device, looked up once per device.
+static hipError_t device_cus(int *cus)
+{
+    constexpr int kMaxDev = 64;
+    static std::atomic<int> cached[kMaxDev];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+    int n = cached[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if ((e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev)) !=
+            hipSuccess)
+            return e;
+        cached[dev].store(n, std::memory_order_relaxed);
+    }
+    *cus = n;
+    return hipSuccess;
+}
+
 hipError_t launch_front(const FrontArgs &a, hipStream_t s)
 {
-    const dim3 grid(((a.W + kCW - 1) / kCW) * ((a.H + kCH - 1) / kCH));
+    const int tiles = ((a.W + kCW - 1) / kCW) * ((a.H + kCH - 1) / kCH);
+    const dim3 grid(tiles);
+    int cus = 0;
+    hipError_t e = device_cus(&cus);
+    if (e != hipSuccess) return e;
+    // a frame whose tiles all get a CU of their own: 16 waves a tile
+    const bool wide = tiles <= cus;
     if (a.nrm) {
         if (a.rf != 0 || a.dn) return hipErrorInvalidValue;   // crease-aware: forest only
         hipLaunchKernelGGL((k_front<0, true>), grid, dim3(kFrontWaves * 64), 0, s, a);
     } else if (a.rf == 0) {
-        hipLaunchKernelGGL((k_front<0, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
+        if (wide) hipLaunchKernelGGL((k_front<0, false, 16>), grid, dim3(16 * 64), 0, s, a);
+        else hipLaunchKernelGGL((k_front<0, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
     } else if (a.rf == 1) {
-        hipLaunchKernelGGL((k_front<1, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
+        if (wide) hipLaunchKernelGGL((k_front<1, false, 16>), grid, dim3(16 * 64), 0, s, a);
+        else hipLaunchKernelGGL((k_front<1, false>), grid, dim3(kFrontWaves * 64), 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
