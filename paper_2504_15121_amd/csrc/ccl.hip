@@ -19,9 +19,8 @@
 // retried from the value the atomic returned.  After the merge a pixel's entry
 // only ever changes to its root, so ordinary loads that see an older value still
 // lead to the right root.
-#include <atomic>
-
 #include "ccl.hpp"
+#include "device.hpp"
 #include "lsq.hpp"
 
 namespace snx {
@@ -581,26 +580,6 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, int64_t n, hipStream_t s)
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value, n);
     return hipGetLastError();
-}
-
-// Compute units of the current device, looked up once per device.
-static hipError_t device_cus(int *cus)
-{
-    constexpr int kMaxDev = 64;
-    static std::atomic<int> cached[kMaxDev];
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
-    int n = cached[dev].load(std::memory_order_relaxed);
-    if (n <= 0) {
-        if ((e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev)) !=
-            hipSuccess)
-            return e;
-        cached[dev].store(n, std::memory_order_relaxed);
-    }
-    *cus = n;
-    return hipSuccess;
 }
 
 hipError_t launch_front(const FrontArgs &a, hipStream_t s)

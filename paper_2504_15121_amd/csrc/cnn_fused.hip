@@ -29,6 +29,7 @@
 // (they add it to the finished FP32 sum), then ReLU and bf16 RNE.
 #include <stdint.h>
 
+#include "device.hpp"
 #include "snx_cnn.hpp"
 
 namespace snx {
@@ -546,19 +547,12 @@ k_cnn_fused(CnnFusedArgs a, const CnnFusedArgs *frames, const int *tile_off, con
 
 }  // namespace
 
-static int cu_count()
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 256;
-    return cus;
-}
-
 hipError_t cnn_forward_fused(const CnnFusedArgs &f, hipStream_t s)
 {
     const int ntiles = cnn_fused_tiles(f.W, f.H);
-    const int cus = cu_count();
+    int cus = 0;
+    hipError_t e = device_cus(&cus);
+    if (e != hipSuccess) return e;
     const int grid = ntiles < cus ? ntiles : cus;
     hipLaunchKernelGGL(k_cnn_fused<false>, dim3(grid), dim3(kThreads), kFusedLds, s, f,
                        (const CnnFusedArgs *)nullptr, (const int *)nullptr, (const int *)nullptr, 0);
@@ -571,7 +565,9 @@ hipError_t cnn_forward_fused_batch(const CnnFusedArgs &common, const CnnFusedArg
                                    const int *tile_off, const int *tile_frame, int n, int total,
                                    hipStream_t s)
 {
-    const int cus = cu_count();
+    int cus = 0;
+    hipError_t e = device_cus(&cus);
+    if (e != hipSuccess) return e;
     const int grid = total < cus ? total : cus;
     if (grid < 1) return hipSuccess;
     hipLaunchKernelGGL(k_cnn_fused<true>, dim3(grid), dim3(kThreads), kFusedLds, s, common, frames,
